@@ -1,0 +1,235 @@
+"""CPU FP64 oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never loads it and
+shares no code with it.
+
+The arithmetic lives in ``lbm_oracle.c`` (a dense D3Q19 LBGK step with pull
+streaming and halfway bounce-back, Guo forcing, macroscopic fields and a
+discrete adjoint) and in ``tiles_ref.py`` (the tiling of Alg. 1).  This module
+builds the C file with gcc and wraps it with numpy arrays; the reductions
+(mass, momentum, permeability) are numpy sums over the oracle's fields.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from . import tiles_ref  # noqa: F401  (re-export)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lbm_oracle.c")
+LIB = os.path.join(HERE, "liblbm_oracle.so")
+
+Q = 19
+_lib = None
+
+
+def build(force=False):
+    """Compile the oracle with gcc: -O2, OpenMP, no FMA contraction, no fast-math."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-o", tmp, SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.oracle_lattice.argtypes = [P, P, P]
+        L.oracle_feq.argtypes = [i32, f64, P, P]
+        L.oracle_guo.argtypes = [f64, P, P, P]
+        L.oracle_collide_node.argtypes = [i32, P, P, f64, P]
+        L.oracle_init.argtypes = [P, P, i32, i32, i32, i32, f64, f64, f64, f64]
+        L.oracle_step.argtypes = [P, P, P, i32, i32, i32, i32, i32, f64, P, f64, f64, f64]
+        L.oracle_run.argtypes = [P, P, P, i32, i32, i32, i32, i32, f64, P, f64, f64, f64, i32]
+        L.oracle_step_nodes.argtypes = [P, P, i32, i32, i32, i32, i32, f64, P, f64, f64, f64, P, i64, P]
+        L.oracle_macroscopic.argtypes = [P, P, i32, i32, i32, i32, P, f64, f64, f64, P, P]
+        L.oracle_pull.argtypes = [P, P, P, i32, i32, i32, i32]
+        L.oracle_pull_transpose.argtypes = [P, P, P, i32, i32, i32, i32]
+        L.oracle_collide_jt_node.argtypes = [P, P, f64, P, P, P]
+        L.oracle_loss_ux.argtypes = [P, P, i32, i32, i32, P, P, P]
+        L.oracle_loss_ux.restype = f64
+        L.oracle_adjoint.argtypes = [P, P, i32, i32, i32, i32, f64, P, i32, P, P]
+        L.oracle_adjoint.restype = f64
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _u8(a):
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def lattice():
+    c = np.zeros((Q, 3), dtype=np.int32)
+    w = np.zeros(Q, dtype=np.float64)
+    opp = np.zeros(Q, dtype=np.int32)
+    lib().oracle_lattice(_p(c), _p(w), _p(opp))
+    return c, w, opp
+
+
+def feq(rho, u, model=0):
+    out = np.zeros(Q)
+    lib().oracle_feq(model, float(rho), _p(_f64(u)), _p(out))
+    return out
+
+
+def guo(tau, u, F):
+    out = np.zeros(Q)
+    lib().oracle_guo(float(tau), _p(_f64(u)), _p(_f64(F)), _p(out))
+    return out
+
+
+def collide_node(fin, F, tau, model=0):
+    out = np.zeros(Q)
+    lib().oracle_collide_node(model, _p(_f64(fin)), _p(_f64(F)), float(tau), _p(out))
+    return out
+
+
+def collide_jt_node(fin, F, tau, lam):
+    eta = np.zeros(Q)
+    gF = np.zeros(3)
+    lib().oracle_collide_jt_node(_p(_f64(fin)), _p(_f64(F)), float(tau), _p(_f64(lam)), _p(eta), _p(gF))
+    return eta, gF
+
+
+def _force_args(force):
+    """force: None, a 3-vector (uniform) or a [3,nz,ny,nx] field."""
+    if force is None:
+        return None, None, 0.0, 0.0, 0.0
+    f = np.asarray(force, dtype=np.float64)
+    if f.ndim == 1:
+        return None, None, float(f[0]), float(f[1]), float(f[2])
+    f = _f64(f)
+    return f, _p(f), 0.0, 0.0, 0.0
+
+
+def init(solid, rho0=1.0, u0=(0.0, 0.0, 0.0), model=0):
+    solid = _u8(solid)
+    nz, ny, nx = solid.shape
+    f = np.zeros((Q, nz, ny, nx))
+    lib().oracle_init(_p(f), _p(solid), nx, ny, nz, model, rho0, *map(float, u0))
+    return f
+
+
+def step(f, solid, tau, force=None, periodic=0, model=0):
+    solid = _u8(solid)
+    nz, ny, nx = solid.shape
+    fa = _f64(f)
+    fb = np.zeros_like(fa)
+    keep, fp, fx, fy, fz = _force_args(force)
+    lib().oracle_step(_p(fa), _p(fb), _p(solid), nx, ny, nz, periodic, model, tau, fp, fx, fy, fz)
+    return fb
+
+
+def run(f, solid, tau, nsteps, force=None, periodic=0, model=0):
+    """nsteps steps; returns the new state (the input is not modified)."""
+    solid = _u8(solid)
+    nz, ny, nx = solid.shape
+    fa = _f64(f).copy()
+    scratch = np.zeros_like(fa)
+    keep, fp, fx, fy, fz = _force_args(force)
+    lib().oracle_run(_p(fa), _p(scratch), _p(solid), nx, ny, nz, periodic, model, tau, fp, fx, fy, fz,
+                     int(nsteps))
+    return fa
+
+
+def step_nodes(f, solid, tau, nodes, force=None, periodic=0, model=0):
+    """One-step update of the listed flat node indices: returns [len(nodes), 19]."""
+    solid = _u8(solid)
+    nz, ny, nx = solid.shape
+    fa = _f64(f)
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.zeros((nodes.size, Q))
+    keep, fp, fx, fy, fz = _force_args(force)
+    lib().oracle_step_nodes(_p(fa), _p(solid), nx, ny, nz, periodic, model, tau, fp, fx, fy, fz, _p(nodes),
+                            nodes.size, _p(out))
+    return out
+
+
+def macroscopic(f, solid, force=None, model=0):
+    """(rho [nz,ny,nx], u [3,nz,ny,nx]) from a stored post-collision state."""
+    solid = _u8(solid)
+    nz, ny, nx = solid.shape
+    fa = _f64(f)
+    rho = np.zeros((nz, ny, nx))
+    u = np.zeros((3, nz, ny, nx))
+    keep, fp, fx, fy, fz = _force_args(force)
+    lib().oracle_macroscopic(_p(fa), _p(solid), nx, ny, nz, model, fp, fx, fy, fz, _p(rho), _p(u))
+    return rho, u
+
+
+def sums(f, solid, force=None, model=0):
+    """FP64 totals {mass, mom_x, mom_y, mom_z, n_fluid} (numpy pairwise sums)."""
+    rho, u = macroscopic(f, solid, force, model)
+    fl = _u8(solid) == 0
+    r = rho[fl]
+    return np.array([r.sum(), (r * u[0][fl]).sum(), (r * u[1][fl]).sum(), (r * u[2][fl]).sum(),
+                     float(fl.sum())])
+
+
+def permeability(f, solid, tau, g_x, rho0=1.0, force=None, model=0):
+    """Darcy permeability k = nu * q / g_x with the superficial flux
+    q = sum_fluid rho u_x / (rho0 * N_box); nu = (tau - 1/2)/3."""
+    rho, u = macroscopic(f, solid, force, model)
+    fl = _u8(solid) == 0
+    nu = (tau - 0.5) / 3.0
+    q = (rho[fl] * u[0][fl]).sum() / (rho0 * solid.size)
+    return nu * q / g_x
+
+
+def pull(s, solid, periodic=0):
+    solid = _u8(solid)
+    nz, ny, nx = solid.shape
+    s = _f64(s)
+    g = np.zeros_like(s)
+    lib().oracle_pull(_p(s), _p(g), _p(solid), nx, ny, nz, periodic)
+    return g
+
+
+def pull_transpose(mu, solid, periodic=0):
+    solid = _u8(solid)
+    nz, ny, nx = solid.shape
+    mu = _f64(mu)
+    out = np.zeros_like(mu)
+    lib().oracle_pull_transpose(_p(mu), _p(out), _p(solid), nx, ny, nz, periodic)
+    return out
+
+
+def loss_ux(s, solid, force_field=None):
+    solid = _u8(solid)
+    nz, ny, nx = solid.shape
+    s = _f64(s)
+    ff = None if force_field is None else _f64(force_field)
+    return lib().oracle_loss_ux(_p(s), _p(solid), nx, ny, nz, _p(ff), None, None)
+
+
+def adjoint(s0, solid, tau, force_field, T, periodic=0):
+    """Returns (L, dL/ds0 [19,...], dL/dF [3,...]) for L = mean u_x at step T."""
+    solid = _u8(solid)
+    nz, ny, nx = solid.shape
+    s0 = _f64(s0)
+    ff = _f64(force_field)
+    gs = np.zeros_like(s0)
+    gF = np.zeros_like(ff)
+    L = lib().oracle_adjoint(_p(s0), _p(solid), nx, ny, nz, periodic, tau, _p(ff), int(T), _p(gs), _p(gF))
+    if not np.isfinite(L):
+        raise MemoryError("oracle_adjoint: allocation failed")
+    return L, gs, gF
