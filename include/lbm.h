@@ -1,0 +1,223 @@
+/*
+ * lbm.h -- C ABI of the tiled sparse-geometry D3Q19 lattice-Boltzmann library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of Tomczak & Szafran, "A new GPU implementation for
+ * lattice-Boltzmann simulations on sparse geometries": the box is covered by
+ * 4x4x4-node tiles, all-solid tiles are dropped (Section 3.1, Alg. 1), and one
+ * fused kernel per time step gathers the 19 distributions of every fluid node
+ * from its upstream neighbours (pull streaming), replaces reads from solid
+ * neighbours by bounce-back, collides with LBGK and stores the result in a
+ * second lattice (Section 3.4, Alg. 2; Eq. 2, 3, 5, 7).  A body force (Guo
+ * forcing), periodic axes, reduced-precision storage and a discrete adjoint
+ * are additions described with each entry point.
+ *
+ * Conventions used throughout:
+ *   - dense arrays are indexed [..][z][y][x] with x fastest, over the PADDED
+ *     box (nx, ny, nz of lbm_tiles);
+ *   - D3Q19 directions: 0 rest; 1 E(+x) 2 N(+y) 3 W(-x) 4 S(-y) 5 T(+z)
+ *     6 B(-z); 7 NE 8 NW 9 SW 10 SE 11 ET 12 EB 13 WT 14 WB 15 NT 16 NB 17 ST
+ *     18 SB (e_3 = W as in the paper's Fig. 1);
+ *   - inside a tile, node (x,y,z) in 0..3 has lane/bit n = x + 4y + 16z
+ *     (the XYZ map, Eq. 11);
+ *   - tile-order buffers are [n_tiles][components][64];
+ *   - device pointers are plain HIP device addresses owned by the caller; the
+ *     library never allocates device memory;
+ *   - every call returns an lbm_status; on failure lbm_last_error() gives a
+ *     thread-local message.  Nothing crosses the ABI as a C++ exception.
+ *   - kernel launches are asynchronous on the context's stream; errors of a
+ *     launch itself are returned by the launching call, faults inside a kernel
+ *     surface at the next synchronising call (lbm_macroscopic*).
+ */
+#ifndef TILED_LBM_H
+#define TILED_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_E_INVAL = -1,       /* bad argument (NULL, tau <= 1/2, bad dims, ...) */
+    LBM_E_NOMEM = -2,       /* host allocation failed */
+    LBM_E_RANGE = -3,       /* a count does not fit the index types */
+    LBM_E_HIP = -4,         /* a HIP runtime call or launch failed */
+    LBM_E_STATE = -5,       /* call not valid in the context's current state */
+    LBM_E_UNSUPPORTED = -6, /* option combination not built */
+    LBM_E_NUMERIC = -7      /* non-finite values found by a checking call */
+} lbm_status;
+
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2 } lbm_storage;
+typedef enum { LBM_QUASI_COMPRESSIBLE = 0, LBM_INCOMPRESSIBLE = 1 } lbm_model;
+enum { LBM_PX = 1, LBM_PY = 2, LBM_PZ = 4 }; /* periodic-axis bits */
+
+/* ------------------------------------------------------------------------
+ * Tiling (host only; no device is touched).
+ * ------------------------------------------------------------------------ */
+
+/* Result of lbm_build_tiles.  Host memory owned by the library; release with
+ * lbm_tiles_free. */
+typedef struct lbm_tiles {
+    int32_t nx, ny, nz;     /* padded box: each non-periodic axis rounded up to a multiple of 4 */
+    int32_t tx, ty, tz;     /* tile grid = padded box / 4 */
+    int32_t periodic;       /* LBM_PX | LBM_PY | LBM_PZ */
+    int32_t n_tiles;        /* kept (non-empty) tiles */
+    int64_t n_fluid;        /* non-solid nodes: the MFLUPS numerator */
+    double eta_t;           /* average tile utilisation n_fluid / (64 n_tiles), Eq. 14 */
+    int32_t *tile_map;      /* [tz][ty][tx]: tile number or -1 for an all-solid tile ("tileMap") */
+    int32_t *tile_xyz;      /* [n_tiles][3]: corner node (x,y,z) of each kept tile, in the
+                               order the scan finds them: z outer, y, x inner ("nonEmptyTiles") */
+    int32_t *nbr;           /* [n_tiles][27]: tile number of the neighbour at offset (dx,dy,dz),
+                               k = (dx+1) + 3(dy+1) + 9(dz+1); 13 is the tile itself; -1 when
+                               all-solid or outside a non-periodic axis; periodic axes wrap */
+    uint64_t *fluid_mask;   /* [n_tiles]: bit x+4y+16z set for a non-solid node ("nodeType") */
+} lbm_tiles;
+
+/* Tile a geometry (Section 3.1, Alg. 1; the tile map and neighbourhood of
+ * Section 3.4).
+ *   solid    host [nz][ny][nx] bytes, nonzero = solid; read only
+ *   nx,ny,nz box size in nodes (> 0)
+ *   periodic LBM_P* bits; a periodic axis must have a length that is a
+ *            multiple of 4 (padding would change the period) -> LBM_E_INVAL
+ *   out      receives a new lbm_tiles
+ * Non-periodic axes are extended with solid nodes up to a multiple of 4.
+ * Returns LBM_E_RANGE if the tile count exceeds INT32_MAX. */
+int lbm_build_tiles(const uint8_t *solid, int32_t nx, int32_t ny, int32_t nz, int32_t periodic,
+                    lbm_tiles **out);
+void lbm_tiles_free(lbm_tiles *tiles);
+
+/* ------------------------------------------------------------------------
+ * Context and device buffers.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_params {
+    double tau;             /* LBGK relaxation time (Eq. 2), > 1/2; nu = (tau - 1/2)/3 */
+    double rho0;            /* reference density: F = rho0 * g, shift of reduced storage */
+    int32_t storage;        /* lbm_storage */
+    int32_t model;          /* lbm_model: Eq. 3+5 (0) or Eq. 4+6 (1) */
+    int32_t f16_log2_scale; /* LBM_F16S: stored h = fp16(2^k (f_i - w_i rho0)), k in [0, 30] */
+    int32_t tiles_per_wg;   /* tiles (wave64s) per workgroup: 1, 2, 4 or 8; 0 = default */
+} lbm_params;
+
+typedef struct lbm_sizes {
+    size_t state_bytes;      /* one lattice: n_tiles * 19 * 64 * sizeof(storage) */
+    size_t table_bytes;      /* device copy of the tiling tables */
+    size_t scratch_bytes;    /* reduction scratch */
+    size_t force_bytes;      /* per-node force field in tile order: n_tiles * 3 * 64 * sizeof(arith) */
+    size_t adjoint_bytes;    /* one adjoint lattice: n_tiles * 19 * 64 * sizeof(arith) */
+    size_t grad_force_bytes; /* force gradient, FP64: n_tiles * 3 * 64 * 8 */
+    size_t dense_nodes;      /* nx * ny * nz of the padded box */
+} lbm_sizes;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Buffer sizes for a tiling and parameter set.  All pointers required. */
+int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *params, lbm_sizes *out);
+
+/* Create a context.
+ *   state_a, state_b  two device lattices of state_bytes each ("two copies of
+ *                     f_i", Section 3.1); a step reads one and writes the other
+ *   tables            device buffer of table_bytes; filled here from `tiles`
+ *   scratch           device buffer of scratch_bytes
+ *   hip_stream        hipStream_t the context launches on (NULL = default stream)
+ * The tables are copied to the device and the stream is synchronised before
+ * returning, so `tiles` may be freed afterwards.  Parameters are validated:
+ * tau > 1/2, known storage and model, f16 scale in [0,30], tiles_per_wg in
+ * {0,1,2,4,8}; the tables are checked (every neighbour index in [-1, n_tiles),
+ * no empty kept tile). */
+int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void *state_a, void *state_b,
+               void *tables, void *scratch, void *hip_stream, lbm_ctx **out);
+int lbm_destroy(lbm_ctx *ctx);
+
+/* f_i = feq_i(rho0, u0) (Eq. 3 or 4) at every fluid node of both lattices, 0 at
+ * solid nodes; the current lattice becomes state_a. */
+int lbm_init(lbm_ctx *ctx, double rho0, double ux, double uy, double uz);
+
+/* Body acceleration g; the force density is F = rho0 * g (Guo forcing).
+ * With g_dense_dev == NULL the force is uniform (gx, gy, gz).  Otherwise
+ * g_dense_dev is a device FP64 field [3][nz][ny][nx] that is converted into
+ * g_tile_buf (force_bytes, caller-owned, must outlive its use) and used from
+ * then on; gx, gy, gz are ignored. */
+int lbm_set_force(lbm_ctx *ctx, double gx, double gy, double gz, const double *g_dense_dev,
+                  void *g_tile_buf);
+
+/* n fused collide-and-stream steps on the context's stream, alternating the
+ * two lattices (Alg. 2).  Asynchronous. */
+int lbm_step(lbm_ctx *ctx, int32_t n);
+
+/* One step from lattice `src` to lattice `dst` (any caller buffers of
+ * state_bytes, e.g. checkpoint slots; src != dst).  Does not change which
+ * lattice is current. */
+int lbm_step_buf(lbm_ctx *ctx, const void *src, void *dst);
+
+/* Pointer to the current lattice (the one the last step wrote). */
+int lbm_current_state(lbm_ctx *ctx, void **state);
+
+/* Density and velocity of the current lattice: rho = sum f*_i and
+ * u = (sum c_i f*_i - F/2) / rho (incompressible: without the division),
+ * i.e. the velocity the last collision used.
+ *   rho_dev  device FP64 [nz][ny][nx] or NULL; 0 at solid and dropped nodes
+ *   u_dev    device FP64 [3][nz][ny][nx] or NULL
+ *   sums     host double[8]: total mass, momentum x/y/z, fluid node count,
+ *            max |u|, number of fluid nodes with a non-finite rho or u, 0.
+ *            Reduced in FP64 in a fixed order (bitwise reproducible).
+ * Synchronises the stream.  Returns LBM_E_NUMERIC (after filling sums) when a
+ * non-finite value was found. */
+int lbm_macroscopic(lbm_ctx *ctx, double *rho_dev, double *u_dev, double sums[8]);
+/* The same for any lattice buffer of the context. */
+int lbm_macroscopic_buf(lbm_ctx *ctx, const void *state, double *rho_dev, double *u_dev, double sums[8]);
+
+/* Darcy permeability of the current lattice along x: k = nu * q / g_x with the
+ * superficial flux q = sum rho u_x / (rho0 * nx*ny*nz).  Synchronises. */
+int lbm_permeability(lbm_ctx *ctx, double g_x, double *k);
+
+/* Dense FP64 copy of a lattice: f_dense_dev [19][nz][ny][nx] (device),
+ * decoded from reduced storage; 0 at solid and dropped nodes.  state == NULL
+ * means the current lattice. */
+int lbm_get_state(lbm_ctx *ctx, const void *state, double *f_dense_dev);
+/* Load a lattice from a dense FP64 array (encoded into the storage type;
+ * solid slots are set to 0).  state == NULL means the current lattice. */
+int lbm_set_state(lbm_ctx *ctx, const double *f_dense_dev, void *state);
+
+/* Tile-order buffer [n_tiles][ncomp][64] of FP64 (dtype 0) or FP32 (dtype 1)
+ * to a dense FP64 [ncomp][nz][ny][nx] device array (0 outside kept tiles). */
+int lbm_tiles_to_dense(lbm_ctx *ctx, const void *tile_buf, int32_t ncomp, int32_t dtype, double *dense_dev);
+
+/* ------------------------------------------------------------------------
+ * Discrete adjoint (quasi-compressible model, FP64 storage).
+ *
+ * Forward: s_t = C(S s_{t-1}, F), S = pull streaming with bounce-back,
+ * C = local LBGK + Guo collision.  Loss L = (1/N_fluid) sum_fluid u_x(s_T).
+ * The adjoint lattices hold eta_t = J_t^T lambda_t (J_t = dC/dg at
+ * g_t = S s_{t-1}, lambda_t = dL/ds_t); lambda_{t-1} = S^T eta_t is formed
+ * on the fly by a reverse gather.  Gradients with respect to the body
+ * acceleration g are accumulated in FP64 tile order [n_tiles][3][64].
+ * The backward sweep is:
+ *     lbm_adjoint_seed(s_{T-1})                      -> eta_T,  gF  = ...
+ *     lbm_adjoint_step(s_{t-2}, eta_t) for t=T..2   -> eta_{t-1}, gF += ...
+ *     lbm_adjoint_final(eta_1)                        -> lambda_0 = dL/ds_0
+ * ------------------------------------------------------------------------ */
+int lbm_adjoint_seed(lbm_ctx *ctx, const void *s_Tm1, void *eta_T, double *grad_g_tile);
+int lbm_adjoint_step(lbm_ctx *ctx, const void *s_tm2, const void *eta_t, void *eta_tm1, double *grad_g_tile);
+int lbm_adjoint_final(lbm_ctx *ctx, const void *eta_1, void *lambda_0);
+
+/* ------------------------------------------------------------------------
+ * Measurement kernels (the paper's "read/write only" and "propagation only"
+ * kernels, Section 4.1): same tiles and launch shape as a step, kind 1 reads
+ * and writes each node's own 19 values, kind 2 performs the full gather and
+ * bounce-back and stores the gathered values without collision.
+ * ------------------------------------------------------------------------ */
+int lbm_calib_step(lbm_ctx *ctx, int32_t kind, const void *src, void *dst);
+
+/* Counts of the current context (any pointer may be NULL). */
+int lbm_info(lbm_ctx *ctx, int32_t *n_tiles, int64_t *n_fluid, int32_t *storage, int32_t *grid_blocks);
+
+const char *lbm_last_error(void);
+const char *lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TILED_LBM_H */

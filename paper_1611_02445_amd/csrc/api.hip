@@ -1,0 +1,361 @@
+// C ABI entry points: parameter validation, buffer sizing, table upload,
+// lattice ping-pong and kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace tlbm;
+
+struct lbm_ctx {
+    lbm_params params;
+    int32_t nx, ny, nz, periodic;
+    int32_t n_tiles;
+    int64_t n_fluid;
+    void *a, *b;        // the two lattices
+    int cur;            // 0: a is current, 1: b is current
+    void *tables;
+    double *scratch;    // [n_tiles][8] partials + [8] final
+    hipStream_t stream;
+    Launch L;
+    Phys P;
+    size_t state_bytes;
+    int device;
+};
+
+namespace {
+
+size_t storage_size(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
+size_t arith_size(int storage) { return storage == LBM_F64 ? 8 : 4; }
+
+int check_params(const lbm_params *p) {
+    if (!p) return fail(LBM_E_INVAL, "NULL params");
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_E_INVAL, "tau must be > 1/2 (got %g)", p->tau);
+    if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LBM_E_INVAL, "rho0 must be > 0 (got %g)", p->rho0);
+    if (p->storage < LBM_F64 || p->storage > LBM_F16S) return fail(LBM_E_INVAL, "unknown storage %d", p->storage);
+    if (p->model != LBM_QUASI_COMPRESSIBLE && p->model != LBM_INCOMPRESSIBLE)
+        return fail(LBM_E_INVAL, "unknown model %d", p->model);
+    if (p->f16_log2_scale < 0 || p->f16_log2_scale > 30)
+        return fail(LBM_E_INVAL, "f16_log2_scale must be in [0, 30] (got %d)", p->f16_log2_scale);
+    const int tpw = p->tiles_per_wg;
+    if (!(tpw == 0 || tpw == 1 || tpw == 2 || tpw == 4 || tpw == 8))
+        return fail(LBM_E_INVAL, "tiles_per_wg must be 0, 1, 2, 4 or 8 (got %d)", tpw);
+    return LBM_OK;
+}
+
+int check_tiles(const lbm_tiles *t) {
+    if (!t) return fail(LBM_E_INVAL, "NULL tiles");
+    if (t->n_tiles < 0) return fail(LBM_E_INVAL, "negative tile count");
+    if (t->n_tiles > 0 && (!t->nbr || !t->fluid_mask || !t->tile_xyz))
+        return fail(LBM_E_INVAL, "tiles without tables");
+    return LBM_OK;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(LBM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int default_tpw(int storage) { return storage == LBM_F64 ? 4 : 4; }
+
+}  // namespace
+
+extern "C" int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *params, lbm_sizes *out) {
+    clear_error();
+    int rc;
+    if ((rc = check_tiles(tiles)) || (rc = check_params(params))) return rc;
+    if (!out) return fail(LBM_E_INVAL, "NULL output");
+    const size_t n = (size_t)tiles->n_tiles;
+    out->state_bytes = n * Q * TILE * storage_size(params->storage);
+    out->table_bytes = TableLayout((int64_t)n).total;
+    out->scratch_bytes = (n + 1) * NSUM * sizeof(double);
+    out->force_bytes = n * 3 * TILE * arith_size(params->storage);
+    out->adjoint_bytes = n * Q * TILE * arith_size(params->storage);
+    out->grad_force_bytes = n * 3 * TILE * sizeof(double);
+    out->dense_nodes = (size_t)tiles->nx * (size_t)tiles->ny * (size_t)tiles->nz;
+    return LBM_OK;
+}
+
+extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void *state_a, void *state_b,
+                          void *tables, void *scratch, void *hip_stream, lbm_ctx **out) {
+    clear_error();
+    int rc;
+    if ((rc = check_tiles(tiles)) || (rc = check_params(params))) return rc;
+    if (!out) return fail(LBM_E_INVAL, "NULL output");
+    *out = nullptr;
+    const int64_t n = tiles->n_tiles;
+    if (n > 0 && (!state_a || !state_b || !tables || !scratch))
+        return fail(LBM_E_INVAL, "lbm_create: NULL device buffer");
+    if (n > 0 && state_a == state_b) return fail(LBM_E_INVAL, "lbm_create: the two lattices must differ");
+    // Validate every table entry the kernels will index with.
+    for (int64_t i = 0; i < n; ++i) {
+        if (tiles->fluid_mask[i] == 0) return fail(LBM_E_INVAL, "lbm_create: kept tile %lld has no fluid node", (long long)i);
+        for (int k = 0; k < 27; ++k) {
+            const int32_t v = tiles->nbr[27 * i + k];
+            if (v < -1 || v >= n) return fail(LBM_E_INVAL, "lbm_create: neighbour index %d out of range", v);
+        }
+        if (tiles->nbr[27 * i + 13] != (int32_t)i) return fail(LBM_E_INVAL, "lbm_create: tile %lld is not its own centre neighbour", (long long)i);
+        for (int a = 0; a < 3; ++a) {
+            const int32_t c = tiles->tile_xyz[3 * i + a];
+            const int32_t lim = a == 0 ? tiles->nx : (a == 1 ? tiles->ny : tiles->nz);
+            if (c < 0 || c % 4 || c + 4 > lim) return fail(LBM_E_INVAL, "lbm_create: tile corner out of the box");
+        }
+    }
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_E_NOMEM, "lbm_create: out of host memory");
+    c->params = *params;
+    if (c->params.tiles_per_wg == 0) c->params.tiles_per_wg = default_tpw(params->storage);
+    c->nx = tiles->nx;
+    c->ny = tiles->ny;
+    c->nz = tiles->nz;
+    c->periodic = tiles->periodic;
+    c->n_tiles = (int32_t)n;
+    c->n_fluid = tiles->n_fluid;
+    c->a = state_a;
+    c->b = state_b;
+    c->cur = 0;
+    c->tables = tables;
+    c->scratch = reinterpret_cast<double *>(scratch);
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->state_bytes = (size_t)n * Q * TILE * storage_size(params->storage);
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+
+    const TableLayout lay(n);
+    if (n > 0) {
+        std::vector<unsigned char> host(lay.total, 0);
+        memcpy(host.data() + lay.mask_off, tiles->fluid_mask, (size_t)n * 8);
+        int32_t *nb = reinterpret_cast<int32_t *>(host.data() + lay.nbr_off);
+        int32_t *xyz = reinterpret_cast<int32_t *>(host.data() + lay.xyz_off);
+        for (int64_t i = 0; i < n; ++i) {
+            for (int k = 0; k < NBR_STRIDE; ++k) nb[NBR_STRIDE * i + k] = k < 27 ? tiles->nbr[27 * i + k] : -1;
+            for (int a = 0; a < 3; ++a) xyz[4 * i + a] = tiles->tile_xyz[3 * i + a];
+            xyz[4 * i + 3] = 0;
+        }
+        hipError_t e = hipMemcpyAsync(tables, host.data(), lay.total, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail(e, "lbm_create: table upload");
+        }
+    }
+    const unsigned char *tb = reinterpret_cast<const unsigned char *>(tables);
+    c->L.stream = c->stream;
+    c->L.n_tiles = (int)n;
+    c->L.tpw = c->params.tiles_per_wg;
+    c->L.grid = (int)((n + c->L.tpw - 1) / c->L.tpw);
+    c->L.tb.mask = reinterpret_cast<const uint64_t *>(tb + lay.mask_off);
+    c->L.tb.nbr = reinterpret_cast<const int32_t *>(tb + lay.nbr_off);
+    c->L.tb.xyz = reinterpret_cast<const int32_t *>(tb + lay.xyz_off);
+    // lattice byte offsets (adjoint lattices are FP64, 8 B) must fit 32 bits
+    c->L.off32 = (size_t)n * Q * TILE * 8 <= (size_t)UINT32_MAX;
+
+    Phys &P = c->P;
+    P = Phys{};
+    P.storage = params->storage;
+    P.model = params->model;
+    P.omega = 1.0 / params->tau;
+    P.kg = 1.0 - 1.0 / (2.0 * params->tau);
+    P.rho0 = params->rho0;
+    P.rho_base = params->storage == LBM_F64 ? 0.0 : params->rho0;
+    P.field = nullptr;
+    P.scale = params->storage == LBM_F16S ? std::ldexp(1.0f, params->f16_log2_scale) : 1.0f;
+    P.inv_scale = 1.0f / P.scale;
+    P.inv_nfluid = c->n_fluid > 0 ? 1.0 / (double)c->n_fluid : 0.0;
+    *out = c;
+    return LBM_OK;
+}
+
+extern "C" int lbm_destroy(lbm_ctx *c) {
+    delete c;
+    return LBM_OK;
+}
+
+static void *cur_state(lbm_ctx *c) { return c->cur ? c->b : c->a; }
+
+#define CHECK_CTX(c)                                                      \
+    do {                                                                  \
+        clear_error();                                                    \
+        if (!(c)) return fail(LBM_E_INVAL, "NULL context");               \
+    } while (0)
+
+static int launched(hipError_t e, const char *what) { return e == hipSuccess ? LBM_OK : hip_fail(e, what); }
+
+extern "C" int lbm_init(lbm_ctx *c, double rho0, double ux, double uy, double uz) {
+    CHECK_CTX(c);
+    if (!(rho0 > 0.0) || !std::isfinite(rho0)) return fail(LBM_E_INVAL, "lbm_init: rho0 must be > 0");
+    Phys P = c->P;
+    P.rho0 = rho0;  // initial density; the storage shift stays at the context's rho0
+    c->cur = 0;
+    return launched(launch_init(c->L, P, c->a, c->b, ux, uy, uz), "lbm_init");
+}
+
+extern "C" int lbm_set_force(lbm_ctx *c, double gx, double gy, double gz, const double *g_dense_dev, void *g_tile_buf) {
+    CHECK_CTX(c);
+    if (!g_dense_dev) {
+        if (!std::isfinite(gx) || !std::isfinite(gy) || !std::isfinite(gz))
+            return fail(LBM_E_INVAL, "lbm_set_force: non-finite force");
+        c->P.field = nullptr;
+        c->P.F[0] = c->params.rho0 * gx;
+        c->P.F[1] = c->params.rho0 * gy;
+        c->P.F[2] = c->params.rho0 * gz;
+        return LBM_OK;
+    }
+    if (!g_tile_buf && c->n_tiles > 0) return fail(LBM_E_INVAL, "lbm_set_force: field given without a tile buffer");
+    hipError_t e = launch_force_to_tiles(c->L, c->P, g_dense_dev, g_tile_buf, c->nx, c->ny, c->nz);
+    if (e != hipSuccess) return hip_fail(e, "lbm_set_force");
+    c->P.field = g_tile_buf;
+    c->P.F[0] = c->P.F[1] = c->P.F[2] = 0.0;
+    return LBM_OK;
+}
+
+extern "C" int lbm_step(lbm_ctx *c, int32_t n) {
+    CHECK_CTX(c);
+    if (n < 0) return fail(LBM_E_INVAL, "lbm_step: negative step count");
+    for (int32_t s = 0; s < n; ++s) {
+        void *src = cur_state(c);
+        void *dst = c->cur ? c->a : c->b;
+        hipError_t e = launch_step(c->L, c->P, src, dst);
+        if (e != hipSuccess) return hip_fail(e, "lbm_step");
+        c->cur ^= 1;
+    }
+    return LBM_OK;
+}
+
+extern "C" int lbm_step_buf(lbm_ctx *c, const void *src, void *dst) {
+    CHECK_CTX(c);
+    if (c->n_tiles > 0 && (!src || !dst)) return fail(LBM_E_INVAL, "lbm_step_buf: NULL lattice");
+    if (src == dst && c->n_tiles > 0) return fail(LBM_E_INVAL, "lbm_step_buf: src and dst must differ");
+    return launched(launch_step(c->L, c->P, src, dst), "lbm_step_buf");
+}
+
+extern "C" int lbm_current_state(lbm_ctx *c, void **state) {
+    CHECK_CTX(c);
+    if (!state) return fail(LBM_E_INVAL, "NULL output");
+    *state = cur_state(c);
+    return LBM_OK;
+}
+
+extern "C" int lbm_macroscopic_buf(lbm_ctx *c, const void *state, double *rho_dev, double *u_dev, double sums[8]) {
+    CHECK_CTX(c);
+    if (!sums) return fail(LBM_E_INVAL, "lbm_macroscopic: NULL sums");
+    if (!state) state = cur_state(c);
+    const size_t N = (size_t)c->nx * c->ny * c->nz;
+    hipError_t e = hipSuccess;
+    if (rho_dev) e = launch_fill(c->stream, rho_dev, N);
+    if (e == hipSuccess && u_dev) e = launch_fill(c->stream, u_dev, 3 * N);
+    double *final_ = c->scratch + (size_t)c->n_tiles * NSUM;
+    if (c->n_tiles == 0) {
+        for (int k = 0; k < NSUM; ++k) sums[k] = 0.0;
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        return launched(e, "lbm_macroscopic");
+    }
+    if (e == hipSuccess) e = launch_macro(c->L, c->P, state, rho_dev, u_dev, c->nx, c->ny, c->nz, c->scratch);
+    if (e == hipSuccess) e = launch_reduce(c->stream, c->scratch, c->n_tiles, final_);
+    if (e == hipSuccess) e = hipMemcpyAsync(sums, final_, NSUM * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_macroscopic");
+    if (sums[6] > 0.0) return fail(LBM_E_NUMERIC, "lbm_macroscopic: %.0f fluid nodes with non-finite values", sums[6]);
+    return LBM_OK;
+}
+
+extern "C" int lbm_macroscopic(lbm_ctx *c, double *rho_dev, double *u_dev, double sums[8]) {
+    CHECK_CTX(c);
+    return lbm_macroscopic_buf(c, cur_state(c), rho_dev, u_dev, sums);
+}
+
+extern "C" int lbm_permeability(lbm_ctx *c, double g_x, double *k) {
+    CHECK_CTX(c);
+    if (!k) return fail(LBM_E_INVAL, "NULL output");
+    if (g_x == 0.0) return fail(LBM_E_INVAL, "lbm_permeability: g_x must be nonzero");
+    double s[8];
+    const int rc = lbm_macroscopic(c, nullptr, nullptr, s);
+    if (rc) return rc;
+    const double nu = (c->params.tau - 0.5) / 3.0;
+    const double nbox = (double)c->nx * (double)c->ny * (double)c->nz;
+    *k = nu * (s[1] / (c->params.rho0 * nbox)) / g_x;
+    return LBM_OK;
+}
+
+extern "C" int lbm_get_state(lbm_ctx *c, const void *state, double *f_dense_dev) {
+    CHECK_CTX(c);
+    if (!f_dense_dev) return fail(LBM_E_INVAL, "lbm_get_state: NULL output");
+    if (!state) state = cur_state(c);
+    const size_t N = (size_t)c->nx * c->ny * c->nz;
+    hipError_t e = launch_fill(c->stream, f_dense_dev, Q * N);
+    if (e == hipSuccess) e = launch_get_state(c->L, c->P, state, f_dense_dev, c->nx, c->ny, c->nz);
+    return launched(e, "lbm_get_state");
+}
+
+extern "C" int lbm_set_state(lbm_ctx *c, const double *f_dense_dev, void *state) {
+    CHECK_CTX(c);
+    if (!f_dense_dev) return fail(LBM_E_INVAL, "lbm_set_state: NULL input");
+    if (!state) state = cur_state(c);
+    return launched(launch_set_state(c->L, c->P, f_dense_dev, state, c->nx, c->ny, c->nz), "lbm_set_state");
+}
+
+extern "C" int lbm_tiles_to_dense(lbm_ctx *c, const void *tile_buf, int32_t ncomp, int32_t dtype, double *dense_dev) {
+    CHECK_CTX(c);
+    if (!tile_buf || !dense_dev) return fail(LBM_E_INVAL, "lbm_tiles_to_dense: NULL buffer");
+    if (ncomp <= 0 || ncomp > 64) return fail(LBM_E_INVAL, "lbm_tiles_to_dense: ncomp must be in 1..64");
+    if (dtype != 0 && dtype != 1) return fail(LBM_E_INVAL, "lbm_tiles_to_dense: dtype must be 0 (f64) or 1 (f32)");
+    const size_t N = (size_t)c->nx * c->ny * c->nz;
+    hipError_t e = launch_fill(c->stream, dense_dev, (size_t)ncomp * N);
+    if (e == hipSuccess) e = launch_tiles_to_dense(c->L, tile_buf, ncomp, dtype, dense_dev, c->nx, c->ny, c->nz);
+    return launched(e, "lbm_tiles_to_dense");
+}
+
+static int adjoint_supported(lbm_ctx *c) {
+    if (c->params.storage != LBM_F64) return fail(LBM_E_UNSUPPORTED, "adjoint: only FP64 storage is built");
+    if (c->params.model != LBM_QUASI_COMPRESSIBLE)
+        return fail(LBM_E_UNSUPPORTED, "adjoint: only the quasi-compressible model is built");
+    return LBM_OK;
+}
+
+extern "C" int lbm_adjoint_seed(lbm_ctx *c, const void *s_Tm1, void *eta_T, double *grad_g_tile) {
+    CHECK_CTX(c);
+    int rc = adjoint_supported(c);
+    if (rc) return rc;
+    if (c->n_tiles > 0 && (!s_Tm1 || !eta_T || !grad_g_tile)) return fail(LBM_E_INVAL, "lbm_adjoint_seed: NULL buffer");
+    return launched(launch_adjoint_seed(c->L, c->P, s_Tm1, eta_T, grad_g_tile), "lbm_adjoint_seed");
+}
+
+extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *s_tm2, const void *eta_t, void *eta_tm1, double *grad_g_tile) {
+    CHECK_CTX(c);
+    int rc = adjoint_supported(c);
+    if (rc) return rc;
+    if (c->n_tiles > 0 && (!s_tm2 || !eta_t || !eta_tm1 || !grad_g_tile))
+        return fail(LBM_E_INVAL, "lbm_adjoint_step: NULL buffer");
+    if (eta_t == eta_tm1 && c->n_tiles > 0) return fail(LBM_E_INVAL, "lbm_adjoint_step: eta buffers must differ");
+    return launched(launch_adjoint_step(c->L, c->P, s_tm2, eta_t, eta_tm1, grad_g_tile), "lbm_adjoint_step");
+}
+
+extern "C" int lbm_adjoint_final(lbm_ctx *c, const void *eta_1, void *lambda_0) {
+    CHECK_CTX(c);
+    int rc = adjoint_supported(c);
+    if (rc) return rc;
+    if (c->n_tiles > 0 && (!eta_1 || !lambda_0)) return fail(LBM_E_INVAL, "lbm_adjoint_final: NULL buffer");
+    if (eta_1 == lambda_0 && c->n_tiles > 0) return fail(LBM_E_INVAL, "lbm_adjoint_final: buffers must differ");
+    return launched(launch_adjoint_final(c->L, c->P, eta_1, lambda_0), "lbm_adjoint_final");
+}
+
+extern "C" int lbm_calib_step(lbm_ctx *c, int32_t kind, const void *src, void *dst) {
+    CHECK_CTX(c);
+    if (kind != 1 && kind != 2) return fail(LBM_E_INVAL, "lbm_calib_step: kind must be 1 or 2");
+    if (c->n_tiles > 0 && (!src || !dst || src == dst)) return fail(LBM_E_INVAL, "lbm_calib_step: bad lattices");
+    return launched(launch_calib(c->L, kind, c->params.storage, src, dst), "lbm_calib_step");
+}
+
+extern "C" int lbm_info(lbm_ctx *c, int32_t *n_tiles, int64_t *n_fluid, int32_t *storage, int32_t *grid_blocks) {
+    CHECK_CTX(c);
+    if (n_tiles) *n_tiles = c->n_tiles;
+    if (n_fluid) *n_fluid = c->n_fluid;
+    if (storage) *storage = c->params.storage;
+    if (grid_blocks) *grid_blocks = c->L.grid;
+    return LBM_OK;
+}

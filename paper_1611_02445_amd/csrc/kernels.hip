@@ -1,0 +1,878 @@
+// gfx950 kernels of the tiled D3Q19 lattice-Boltzmann method.
+//
+// Mapping (re-designed for CDNA4 from the paper's Section 3.1 thread mapping):
+// one 4x4x4 tile = one wave64, lane n = x + 4y + 16z.  A lattice is stored
+// per tile as 19 contiguous blocks of 64 values ("data block", Section 3.2),
+// so the wave reads and writes its own node values as whole 64-lane vectors.
+//
+// Streaming is a pull (gather) fused with collision (Section 2.4, Alg. 2).
+// For every direction the wave combines, on the scalar unit, the 64-bit fluid
+// masks of the tile and of the neighbours the direction reaches into a single
+// 64-bit "source is fluid" mask; that mask is then used directly as the lane
+// condition (inverse ballot) selecting between the upstream value and the
+// bounce-back value at the node itself.  Neighbour tile numbers come from the
+// 27-entry row of the tiling table (the 3x3x3 window of the tile map).
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "kernels.hpp"
+
+namespace tlbm {
+
+// ---------------------------------------------------------------------------
+// storage codecs
+//   F64 : f_i as double, arithmetic in double
+//   F32 : d_i = f_i - w_i rho0 as float, arithmetic in float
+//   F16S: h_i = fp16(s * d_i), s = 2^k, arithmetic in float
+// The kernels work on the shifted value d_i = f_i - w_i rho_base (rho_base = 0
+// for F64).  Opposite directions have equal weights, so a bounce-back copy
+// needs no re-shift.
+// ---------------------------------------------------------------------------
+template <int ST> struct Codec;
+template <> struct Codec<LBM_F64> {
+    using S = double;
+    using T = double;
+    static __device__ __forceinline__ T dec(S v, float) { return v; }
+    static __device__ __forceinline__ S enc(T v, float) { return v; }
+};
+template <> struct Codec<LBM_F32> {
+    using S = float;
+    using T = float;
+    static __device__ __forceinline__ T dec(S v, float) { return v; }
+    static __device__ __forceinline__ S enc(T v, float) { return v; }
+};
+template <> struct Codec<LBM_F16S> {
+    using S = _Float16;
+    using T = float;
+    static __device__ __forceinline__ T dec(S v, float inv_scale) { return (float)v * inv_scale; }
+    static __device__ __forceinline__ S enc(T v, float scale) { return (_Float16)(v * scale); }
+};
+
+// ---------------------------------------------------------------------------
+// wave -> tile mapping
+// ---------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Re-number them so that every XCD works through one contiguous range of
+// tiles: neighbouring tiles, which share partially used cache lines, are then
+// processed by the same L2.
+__device__ __forceinline__ int remap_block(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int xcd = b & 7, local = b >> 3;
+    return xcd * q + (xcd < r ? xcd : r) + local;
+}
+
+__device__ __forceinline__ int wave_tile() {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wpb = (int)(blockDim.x >> 6);
+    return remap_block((int)blockIdx.x, (int)gridDim.x) * wpb + wave;
+}
+
+__device__ __forceinline__ bool lane_on(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// ---------------------------------------------------------------------------
+// neighbourhood of a tile (wave-uniform: lives in SGPRs)
+// ---------------------------------------------------------------------------
+struct Nbhd {
+    int nb[27];
+    uint64_t m[27];
+};
+
+__device__ __forceinline__ void load_nbhd(Nbhd &h, const DevTables &tb, int t) {
+    const int32_t *row = tb.nbr + (size_t)t * NBR_STRIDE;
+#pragma unroll
+    for (int k = 0; k < 27; ++k) h.nb[k] = row[k];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+        const int j = h.nb[k];
+        const uint64_t mk = tb.mask[j < 0 ? 0 : j];
+        h.m[k] = j < 0 ? 0ull : mk;
+    }
+}
+
+// lanes whose source node (x+sx, y+sy, z+sz) leaves the tile exactly along the
+// axes flagged bx, by, bz
+constexpr uint64_t region_mask(int sx, int sy, int sz, int bx, int by, int bz) {
+    uint64_t r = 0;
+    for (int n = 0; n < 64; ++n) {
+        const int x = n & 3, y = (n >> 2) & 3, z = n >> 4;
+        const int cx = (x + sx < 0 || x + sx > 3), cy = (y + sy < 0 || y + sy > 3), cz = (z + sz < 0 || z + sz > 3);
+        if (cx == bx && cy == by && cz == bz) r |= 1ull << n;
+    }
+    return r;
+}
+
+// bits of the neighbour mask that the lanes of one region read
+template <int SX, int SY, int SZ, int BX, int BY, int BZ>
+__device__ __forceinline__ uint64_t region_fluid(const Nbhd &h) {
+    if constexpr ((BX && !SX) || (BY && !SY) || (BZ && !SZ)) {
+        return 0ull;
+    } else {
+        constexpr uint64_t R = region_mask(SX, SY, SZ, BX, BY, BZ);
+        constexpr int k = 13 + BX * SX + 3 * BY * SY + 9 * BZ * SZ;
+        constexpr int off = SX + 4 * SY + 16 * SZ - 4 * BX * SX - 16 * BY * SY - 64 * BZ * SZ;
+        if constexpr (R == 0) return 0ull;
+        const uint64_t mk = h.m[k];
+        const uint64_t sh = off >= 0 ? (mk >> off) : (mk << (-off));
+        return sh & R;
+    }
+}
+
+// 64-bit mask: bit n set when lane n's source node exists and is fluid
+template <int SX, int SY, int SZ>
+__device__ __forceinline__ uint64_t source_fluid(const Nbhd &h) {
+    return region_fluid<SX, SY, SZ, 0, 0, 0>(h) | region_fluid<SX, SY, SZ, 1, 0, 0>(h) |
+           region_fluid<SX, SY, SZ, 0, 1, 0>(h) | region_fluid<SX, SY, SZ, 1, 1, 0>(h) |
+           region_fluid<SX, SY, SZ, 0, 0, 1>(h) | region_fluid<SX, SY, SZ, 1, 0, 1>(h) |
+           region_fluid<SX, SY, SZ, 0, 1, 1>(h) | region_fluid<SX, SY, SZ, 1, 1, 1>(h);
+}
+
+template <int SX, int SY, int SZ, int BX, int BY, int BZ>
+__device__ __forceinline__ int region_tile(const Nbhd &h, int tile) {
+    if constexpr ((BX && !SX) || (BY && !SY) || (BZ && !SZ) || (!BX && !BY && !BZ)) {
+        return tile;
+    } else {
+        constexpr uint64_t R = region_mask(SX, SY, SZ, BX, BY, BZ);
+        constexpr int k = 13 + BX * SX + 3 * BY * SY + 9 * BZ * SZ;
+        return lane_on(R) ? h.nb[k] : tile;
+    }
+}
+
+// tile holding lane's source node (garbage where the source is outside)
+template <int SX, int SY, int SZ>
+__device__ __forceinline__ int source_tile(const Nbhd &h) {
+    int t = h.nb[13];
+    t = region_tile<SX, SY, SZ, 1, 0, 0>(h, t);
+    t = region_tile<SX, SY, SZ, 0, 1, 0>(h, t);
+    t = region_tile<SX, SY, SZ, 1, 1, 0>(h, t);
+    t = region_tile<SX, SY, SZ, 0, 0, 1>(h, t);
+    t = region_tile<SX, SY, SZ, 1, 0, 1>(h, t);
+    t = region_tile<SX, SY, SZ, 0, 1, 1>(h, t);
+    t = region_tile<SX, SY, SZ, 1, 1, 1>(h, t);
+    return t;
+}
+
+// lane index of the source node inside its tile (coordinates wrap mod 4)
+template <int SX, int SY, int SZ>
+__device__ __forceinline__ int source_lane(int lane) {
+    const int x = SX ? ((lane + SX) & 3) : (lane & 3);
+    const int y = SY ? ((lane + 4 * SY) & 12) : (lane & 12);
+    const int z = SZ ? ((lane + 16 * SZ) & 48) : (lane & 48);
+    return x | y | z;
+}
+
+template <typename OffT, typename S>
+__device__ __forceinline__ S load_at(const char *base, OffT off) {
+    return *reinterpret_cast<const S *>(base + off);
+}
+
+// Gather of direction I for this lane: the value of direction I at the source
+// node x - c_I (REV = false: pull streaming S) or x + c_I (REV = true: its
+// transpose S^T), or, when that node is solid or missing, the value of the
+// opposite direction at the node itself (halfway bounce-back).
+template <int I, bool REV, typename S, typename OffT>
+__device__ __forceinline__ S gather_one(const Nbhd &h, const char *base, int t, int lane) {
+    constexpr OffT TB = (OffT)(Q * TILE * sizeof(S));  // bytes per tile
+    if constexpr (I == 0) {
+        return load_at<OffT, S>(base, (OffT)t * TB + (OffT)(lane * sizeof(S)));
+    } else {
+        constexpr int SX = REV ? CX[I] : -CX[I];
+        constexpr int SY = REV ? CY[I] : -CY[I];
+        constexpr int SZ = REV ? CZ[I] : -CZ[I];
+        constexpr int OP = opposite(I);
+        const uint64_t ok_mask = source_fluid<SX, SY, SZ>(h);
+        const int tile = source_tile<SX, SY, SZ>(h);
+        const int sn = source_lane<SX, SY, SZ>(lane);
+        const OffT o_pull = (OffT)tile * TB + (OffT)((I * TILE + sn) * (int)sizeof(S));
+        const OffT o_bb = (OffT)t * TB + (OffT)((OP * TILE + lane) * (int)sizeof(S));
+        return load_at<OffT, S>(base, lane_on(ok_mask) ? o_pull : o_bb);
+    }
+}
+
+template <bool REV, typename S, typename OffT, int... Is>
+__device__ __forceinline__ void gather_all_impl(S (&v)[Q], const Nbhd &h, const char *base, int t, int lane,
+                                                std::integer_sequence<int, Is...>) {
+    ((v[Is] = gather_one<Is, REV, S, OffT>(h, base, t, lane)), ...);
+}
+
+template <bool REV, typename S, typename OffT>
+__device__ __forceinline__ void gather_all(S (&v)[Q], const Nbhd &h, const char *base, int t, int lane) {
+    gather_all_impl<REV, S, OffT>(v, h, base, t, lane, std::make_integer_sequence<int, Q>{});
+}
+
+// ---------------------------------------------------------------------------
+// collision: LBGK (Eq. 2, 7) with the quasi-compressible (Eq. 3, 5) or
+// incompressible (Eq. 4, 6) equilibrium and Guo forcing, on shifted values
+// d_i = f_i - w_i rho_base:
+//   drho = sum d, rho = rho_base + drho, j = sum c d,
+//   u = (j + F/2)/rho (model 0) or j + F/2 (model 1),
+//   deq_i = w_i (drho + rho P_i) (model 0) or w_i (drho + P_i) (model 1),
+//   P_i = 3 c.u + 4.5 (c.u)^2 - 1.5 u.u,
+//   d*_i = d_i + omega (deq_i - d_i) + kg w_i (3 (c_i - u).F + 9 (c_i.u)(c_i.F))
+// ---------------------------------------------------------------------------
+template <typename T, int MODEL>
+__device__ __forceinline__ void collide(T (&d)[Q], T rho_base, T omega, T kg, T Fx, T Fy, T Fz) {
+    T drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        drho += d[i];
+        if (CX[i]) jx += CX[i] > 0 ? d[i] : -d[i];
+        if (CY[i]) jy += CY[i] > 0 ? d[i] : -d[i];
+        if (CZ[i]) jz += CZ[i] > 0 ? d[i] : -d[i];
+    }
+    const T rho = rho_base + drho;
+    T ux = jx + T(0.5) * Fx, uy = jy + T(0.5) * Fy, uz = jz + T(0.5) * Fz;
+    if constexpr (MODEL == LBM_QUASI_COMPRESSIBLE) {
+        const T ir = T(1) / rho;
+        ux *= ir;
+        uy *= ir;
+        uz *= ir;
+    }
+    const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
+    const T uF = ux * Fx + uy * Fy + uz * Fz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T w = T(weight(i));
+        const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
+        const T cF = T(CX[i]) * Fx + T(CY[i]) * Fy + T(CZ[i]) * Fz;
+        const T P = T(3) * cu + T(4.5) * cu * cu - usq;
+        const T deq = (MODEL == LBM_QUASI_COMPRESSIBLE) ? w * (drho + rho * P) : w * (drho + P);
+        const T src = kg * w * (T(3) * (cF - uF) + T(9) * cu * cF);
+        d[i] = d[i] + omega * (deq - d[i]) + src;
+    }
+}
+
+struct KArgs {
+    const char *src;
+    char *dst;
+    DevTables tb;
+    int n_tiles;
+    Phys P;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_force(const Phys &P, int t, int lane, T &Fx, T &Fy, T &Fz) {
+    if (P.field) {
+        const T *f = reinterpret_cast<const T *>(P.field) + (size_t)t * 3 * TILE + lane;
+        Fx = f[0];
+        Fy = f[TILE];
+        Fz = f[2 * TILE];
+    } else {
+        Fx = T(P.F[0]);
+        Fy = T(P.F[1]);
+        Fz = T(P.F[2]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the fused step (Alg. 2): gather with bounce-back, collide, store
+// ---------------------------------------------------------------------------
+template <int ST, int MODEL, typename OffT>
+__global__ __launch_bounds__(512) void k_step(KArgs a) {
+    using C = Codec<ST>;
+    using S = typename C::S;
+    using T = typename C::T;
+    const int t = wave_tile();
+    if (t >= a.n_tiles) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t own = a.tb.mask[t];
+    if (!lane_on(own)) return;  // solid nodes neither read nor write
+    Nbhd h;
+    load_nbhd(h, a.tb, t);
+    S raw[Q];
+    gather_all<false, S, OffT>(raw, h, a.src, t, lane);
+    T d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = C::dec(raw[i], a.P.inv_scale);
+    T Fx, Fy, Fz;
+    load_force<T>(a.P, t, lane, Fx, Fy, Fz);
+    collide<T, MODEL>(d, T(a.P.rho_base), T(a.P.omega), T(a.P.kg), Fx, Fy, Fz);
+    S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + lane;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[i * TILE] = C::enc(d[i], a.P.scale);
+}
+
+// the paper's measurement kernels (Section 4.1): kind 1 "read/write only",
+// kind 2 "propagation only"
+template <typename S, int KIND, typename OffT>
+__global__ __launch_bounds__(512) void k_calib(KArgs a) {
+    const int t = wave_tile();
+    if (t >= a.n_tiles) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t own = a.tb.mask[t];
+    if (!lane_on(own)) return;
+    S v[Q];
+    if constexpr (KIND == 1) {
+        const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + lane;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = in[i * TILE];
+    } else {
+        Nbhd h;
+        load_nbhd(h, a.tb, t);
+        gather_all<false, S, OffT>(v, h, a.src, t, lane);
+    }
+    S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + lane;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[i * TILE] = v[i];
+}
+
+// ---------------------------------------------------------------------------
+// initial state: feq(rho0, u0) at fluid nodes of both lattices, 0 at solid
+// ---------------------------------------------------------------------------
+template <int ST>
+__global__ __launch_bounds__(512) void k_init(KArgs a, char *b, double ux, double uy, double uz) {
+    using C = Codec<ST>;
+    using S = typename C::S;
+    const int t = wave_tile();
+    if (t >= a.n_tiles) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const bool fl = (a.tb.mask[t] >> lane) & 1;
+    const double rho = a.P.rho0;
+    const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
+    S *pa = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + lane;
+    S *pb = reinterpret_cast<S *>(b) + (size_t)t * Q * TILE + lane;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+        const double P = 3.0 * cu + 4.5 * cu * cu - usq;
+        const double feq = (a.P.model == LBM_QUASI_COMPRESSIBLE) ? weight(i) * rho * (1.0 + P) : weight(i) * (rho + P);
+        const double dv = feq - weight(i) * a.P.rho_base;
+        const S v = fl ? C::enc((typename C::T)dv, a.P.scale) : S(0);
+        pa[i * TILE] = v;
+        pb[i * TILE] = v;
+    }
+}
+
+__global__ void k_fill(double *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+__device__ __forceinline__ size_t dense_index(const int *xyz, int lane, int nx, int ny) {
+    const int x = xyz[0] + (lane & 3), y = xyz[1] + ((lane >> 2) & 3), z = xyz[2] + (lane >> 4);
+    return (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * (size_t)z);
+}
+
+// deterministic wave-wide sum / max (fixed butterfly)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// macroscopic fields of a stored post-collision lattice + per-tile FP64
+// partial sums: rho = sum f*, u = (sum c f* - F/2)/rho
+// ---------------------------------------------------------------------------
+template <int ST>
+__global__ __launch_bounds__(512) void k_macro(KArgs a, double *rho_out, double *u_out, int nx, int ny, int nz,
+                                              double *partials) {
+    using C = Codec<ST>;
+    using S = typename C::S;
+    using T = typename C::T;
+    const int t = wave_tile();
+    if (t >= a.n_tiles) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const bool fl = (a.tb.mask[t] >> lane) & 1;
+    const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + lane;
+    double drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double v = (double)C::dec(in[i * TILE], a.P.inv_scale);
+        drho += v;
+        jx += CX[i] * v;
+        jy += CY[i] * v;
+        jz += CZ[i] * v;
+    }
+    T Fx, Fy, Fz;
+    load_force<T>(a.P, t, lane, Fx, Fy, Fz);
+    const double rho = a.P.rho_base + drho;
+    const double mx = jx - 0.5 * (double)Fx, my = jy - 0.5 * (double)Fy, mz = jz - 0.5 * (double)Fz;
+    double ux = mx, uy = my, uz = mz;
+    if (a.P.model == LBM_QUASI_COMPRESSIBLE) {
+        ux = mx / rho;
+        uy = my / rho;
+        uz = mz / rho;
+    }
+    if (fl) {
+        const size_t N = (size_t)nx * ny * nz;
+        const size_t n = dense_index(a.tb.xyz + 4 * (size_t)t, lane, nx, ny);
+        if (rho_out) rho_out[n] = rho;
+        if (u_out) {
+            u_out[n] = ux;
+            u_out[N + n] = uy;
+            u_out[2 * N + n] = uz;
+        }
+    }
+    const bool finite = isfinite(rho) && isfinite(ux) && isfinite(uy) && isfinite(uz);
+    const double s0 = wave_sum(fl ? rho : 0.0);
+    const double s1 = wave_sum(fl ? rho * ux : 0.0);
+    const double s2 = wave_sum(fl ? rho * uy : 0.0);
+    const double s3 = wave_sum(fl ? rho * uz : 0.0);
+    const double s4 = wave_sum(fl ? 1.0 : 0.0);
+    const double s5 = wave_max(fl && finite ? sqrt(ux * ux + uy * uy + uz * uz) : 0.0);
+    const double s6 = wave_sum(fl && !finite ? 1.0 : 0.0);
+    if (lane == 0) {
+        double *p = partials + (size_t)t * NSUM;
+        p[0] = s0;
+        p[1] = s1;
+        p[2] = s2;
+        p[3] = s3;
+        p[4] = s4;
+        p[5] = s5;
+        p[6] = s6;
+        p[7] = 0.0;
+    }
+}
+
+// one workgroup reduces the per-tile partials in a fixed order
+constexpr int RED_THREADS = 512;
+__global__ __launch_bounds__(RED_THREADS) void k_reduce(const double *partials, int n_tiles, double *out) {
+    __shared__ double sh[NSUM][RED_THREADS];
+    const int tid = (int)threadIdx.x;
+    double acc[NSUM];
+#pragma unroll
+    for (int c = 0; c < NSUM; ++c) acc[c] = 0.0;
+    for (int j = tid; j < n_tiles; j += RED_THREADS) {
+#pragma unroll
+        for (int c = 0; c < NSUM; ++c) {
+            const double v = partials[(size_t)j * NSUM + c];
+            acc[c] = (c == 5) ? fmax(acc[c], v) : acc[c] + v;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NSUM; ++c) sh[c][tid] = acc[c];
+    __syncthreads();
+    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+#pragma unroll
+            for (int c = 0; c < NSUM; ++c)
+                sh[c][tid] = (c == 5) ? fmax(sh[c][tid], sh[c][tid + s]) : sh[c][tid] + sh[c][tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid < NSUM) out[tid] = sh[tid][0];
+}
+
+// ---------------------------------------------------------------------------
+// dense <-> tile conversions
+// ---------------------------------------------------------------------------
+template <int ST>
+__global__ __launch_bounds__(512) void k_get_state(KArgs a, double *dense, int nx, int ny, int nz) {
+    using C = Codec<ST>;
+    using S = typename C::S;
+    const int t = wave_tile();
+    if (t >= a.n_tiles) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const bool fl = (a.tb.mask[t] >> lane) & 1;
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t n = dense_index(a.tb.xyz + 4 * (size_t)t, lane, nx, ny);
+    const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + lane;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double v = (double)C::dec(in[i * TILE], a.P.inv_scale) + weight(i) * a.P.rho_base;
+        dense[(size_t)i * N + n] = fl ? v : 0.0;
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(512) void k_set_state(KArgs a, const double *dense, int nx, int ny, int nz) {
+    using C = Codec<ST>;
+    using S = typename C::S;
+    using T = typename C::T;
+    const int t = wave_tile();
+    if (t >= a.n_tiles) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const bool fl = (a.tb.mask[t] >> lane) & 1;
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t n = dense_index(a.tb.xyz + 4 * (size_t)t, lane, nx, ny);
+    S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + lane;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double v = dense[(size_t)i * N + n] - weight(i) * a.P.rho_base;
+        out[i * TILE] = fl ? C::enc((T)v, a.P.scale) : S(0);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_force_to_tiles(KArgs a, const double *g, T *out, int nx, int ny, int nz) {
+    const int t = wave_tile();
+    if (t >= a.n_tiles) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const bool fl = (a.tb.mask[t] >> lane) & 1;
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t n = dense_index(a.tb.xyz + 4 * (size_t)t, lane, nx, ny);
+    T *o = out + (size_t)t * 3 * TILE + lane;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o[c * TILE] = fl ? (T)(a.P.rho0 * g[(size_t)c * N + n]) : T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_tiles_to_dense(KArgs a, const T *in, int ncomp, double *dense, int nx, int ny,
+                                                       int nz) {
+    const int t = wave_tile();
+    if (t >= a.n_tiles) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const bool fl = (a.tb.mask[t] >> lane) & 1;
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t n = dense_index(a.tb.xyz + 4 * (size_t)t, lane, nx, ny);
+    for (int c = 0; c < ncomp; ++c) dense[(size_t)c * N + n] = fl ? (double)in[((size_t)t * ncomp + c) * TILE + lane] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// discrete adjoint (quasi-compressible, FP64)
+//
+// For the local collision C(g, F) with rho = sum g, u = (sum c g + F/2)/rho:
+//   (J^T lam)_j = (1 - 1/tau) lam_j + A + V.(c_j - u)/rho
+//   A   = (1/tau) sum_i lam_i w_i (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
+//   V   = sum_i lam_i [ (rho/tau) w_i (3 c_i + 9 (c_i.u) c_i - 3 u)
+//                       + kg w_i (9 (c_i.F) c_i - 3 F) ]
+//   (dC/dF)^T lam = V/(2 rho) + kg sum_i lam_i w_i (3 (c_i - u) + 9 (c_i.u) c_i)
+// computed with the sums p = sum lam w (rho/tau (3 + 9 c.u) + 9 kg c.F) c,
+// r = sum lam w (3 + 9 c.u) c and q = sum lam w.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void collide_jt(const double (&g)[Q], const double (&lam)[Q], double omega, double kg,
+                                           double Fx, double Fy, double Fz, double (&eta)[Q], double &gx,
+                                           double &gy, double &gz) {
+    double rho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rho += g[i];
+        jx += CX[i] * g[i];
+        jy += CY[i] * g[i];
+        jz += CZ[i] * g[i];
+    }
+    const double ir = 1.0 / rho;
+    const double ux = (jx + 0.5 * Fx) * ir, uy = (jy + 0.5 * Fy) * ir, uz = (jz + 0.5 * Fz) * ir;
+    const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
+    const double ro = rho * omega;
+    double A = 0, q = 0, px = 0, py = 0, pz = 0, rx = 0, ry = 0, rz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double w = weight(i);
+        const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+        const double cF = CX[i] * Fx + CY[i] * Fy + CZ[i] * Fz;
+        const double lw = lam[i] * w;
+        A += lw * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq);
+        q += lw;
+        const double a3 = 3.0 + 9.0 * cu;
+        const double pi = lw * (ro * a3 + 9.0 * kg * cF);
+        const double ri = lw * a3;
+        px += CX[i] * pi;
+        py += CY[i] * pi;
+        pz += CZ[i] * pi;
+        rx += CX[i] * ri;
+        ry += CY[i] * ri;
+        rz += CZ[i] * ri;
+    }
+    A *= omega;
+    const double Vx = px - q * (3.0 * ro * ux + 3.0 * kg * Fx);
+    const double Vy = py - q * (3.0 * ro * uy + 3.0 * kg * Fy);
+    const double Vz = pz - q * (3.0 * ro * uz + 3.0 * kg * Fz);
+    const double Vu = Vx * ux + Vy * uy + Vz * uz;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const double Vc = CX[j] * Vx + CY[j] * Vy + CZ[j] * Vz;
+        eta[j] = (1.0 - omega) * lam[j] + A + (Vc - Vu) * ir;
+    }
+    gx = 0.5 * Vx * ir + kg * (rx - 3.0 * q * ux);
+    gy = 0.5 * Vy * ir + kg * (ry - 3.0 * q * uy);
+    gz = 0.5 * Vz * ir + kg * (rz - 3.0 * q * uz);
+}
+
+struct AdjArgs {
+    const char *s;      // forward lattice feeding the forward gather
+    const char *eta_in; // adjoint lattice feeding the reverse gather
+    char *out;          // adjoint lattice written
+    double *grad;       // [n_tiles][3][64] FP64, dL/dg
+    DevTables tb;
+    int n_tiles;
+    Phys P;
+};
+
+// seed: from s_{T-1}: g_T = S s_{T-1}, s_T = C(g_T), lam_T = dL/ds_T,
+// eta_T = J_T^T lam_T, grad = rho0 [(dC/dF)^T lam_T + dL/dF]
+template <typename OffT>
+__global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
+    const int t = wave_tile();
+    if (t >= a.n_tiles) return;
+    const int lane = (int)(threadIdx.x & 63);
+    double *eo = reinterpret_cast<double *>(a.out) + (size_t)t * Q * TILE + lane;
+    double *go = a.grad + (size_t)t * 3 * TILE + lane;
+    const uint64_t own = a.tb.mask[t];
+    if (!lane_on(own)) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) eo[i * TILE] = 0.0;
+        go[0] = go[TILE] = go[2 * TILE] = 0.0;
+        return;
+    }
+    Nbhd h;
+    load_nbhd(h, a.tb, t);
+    double g[Q];
+    gather_all<false, double, OffT>(g, h, a.s, t, lane);
+    double Fx, Fy, Fz;
+    load_force<double>(a.P, t, lane, Fx, Fy, Fz);
+    double s[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s[i] = g[i];
+    collide<double, LBM_QUASI_COMPRESSIBLE>(s, 0.0, a.P.omega, a.P.kg, Fx, Fy, Fz);
+    double rT = 0, jx = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rT += s[i];
+        jx += CX[i] * s[i];
+    }
+    const double irT = 1.0 / rT;
+    const double uxT = (jx - 0.5 * Fx) * irT;
+    double lam[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lam[i] = (CX[i] - uxT) * irT * a.P.inv_nfluid;
+    double eta[Q], gx, gy, gz;
+    collide_jt(g, lam, a.P.omega, a.P.kg, Fx, Fy, Fz, eta, gx, gy, gz);
+    gx += -0.5 * irT * a.P.inv_nfluid;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) eo[i * TILE] = eta[i];
+    go[0] = a.P.rho0 * gx;
+    go[TILE] = a.P.rho0 * gy;
+    go[2 * TILE] = a.P.rho0 * gz;
+}
+
+// step: lam_{t-1} = S^T eta_t (reverse gather), g_{t-1} = S s_{t-2},
+// eta_{t-1} = J^T lam_{t-1}, grad += rho0 (dC/dF)^T lam_{t-1}
+template <typename OffT>
+__global__ __launch_bounds__(512) void k_adj_step(AdjArgs a) {
+    const int t = wave_tile();
+    if (t >= a.n_tiles) return;
+    const int lane = (int)(threadIdx.x & 63);
+    double *eo = reinterpret_cast<double *>(a.out) + (size_t)t * Q * TILE + lane;
+    const uint64_t own = a.tb.mask[t];
+    if (!lane_on(own)) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) eo[i * TILE] = 0.0;
+        return;
+    }
+    Nbhd h;
+    load_nbhd(h, a.tb, t);
+    double lam[Q], g[Q];
+    gather_all<true, double, OffT>(lam, h, a.eta_in, t, lane);
+    gather_all<false, double, OffT>(g, h, a.s, t, lane);
+    double Fx, Fy, Fz;
+    load_force<double>(a.P, t, lane, Fx, Fy, Fz);
+    double eta[Q], gx, gy, gz;
+    collide_jt(g, lam, a.P.omega, a.P.kg, Fx, Fy, Fz, eta, gx, gy, gz);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) eo[i * TILE] = eta[i];
+    double *go = a.grad + (size_t)t * 3 * TILE + lane;
+    go[0] += a.P.rho0 * gx;
+    go[TILE] += a.P.rho0 * gy;
+    go[2 * TILE] += a.P.rho0 * gz;
+}
+
+// final: lam_0 = S^T eta_1
+template <typename OffT>
+__global__ __launch_bounds__(512) void k_adj_final(AdjArgs a) {
+    const int t = wave_tile();
+    if (t >= a.n_tiles) return;
+    const int lane = (int)(threadIdx.x & 63);
+    double *lo = reinterpret_cast<double *>(a.out) + (size_t)t * Q * TILE + lane;
+    const uint64_t own = a.tb.mask[t];
+    if (!lane_on(own)) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lo[i * TILE] = 0.0;
+        return;
+    }
+    Nbhd h;
+    load_nbhd(h, a.tb, t);
+    double lam[Q];
+    gather_all<true, double, OffT>(lam, h, a.eta_in, t, lane);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lo[i * TILE] = lam[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static KArgs make_args(const Launch &L, const Phys &P, const void *src, void *dst) {
+    KArgs a;
+    a.src = reinterpret_cast<const char *>(src);
+    a.dst = reinterpret_cast<char *>(dst);
+    a.tb = L.tb;
+    a.n_tiles = L.n_tiles;
+    a.P = P;
+    return a;
+}
+
+static dim3 block_of(const Launch &L) { return dim3(64 * L.tpw); }
+
+template <int ST, int MODEL>
+static hipError_t step_t(const Launch &L, const KArgs &a) {
+    if (L.off32)
+        hipLaunchKernelGGL((k_step<ST, MODEL, uint32_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
+    else
+        hipLaunchKernelGGL((k_step<ST, MODEL, uint64_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const Launch &L, const Phys &P, const void *src, void *dst) {
+    if (L.n_tiles == 0) return hipSuccess;
+    const KArgs a = make_args(L, P, src, dst);
+    const bool inc = P.model == LBM_INCOMPRESSIBLE;
+    switch (P.storage) {
+    case LBM_F64: return inc ? step_t<LBM_F64, LBM_INCOMPRESSIBLE>(L, a) : step_t<LBM_F64, LBM_QUASI_COMPRESSIBLE>(L, a);
+    case LBM_F32: return inc ? step_t<LBM_F32, LBM_INCOMPRESSIBLE>(L, a) : step_t<LBM_F32, LBM_QUASI_COMPRESSIBLE>(L, a);
+    case LBM_F16S: return inc ? step_t<LBM_F16S, LBM_INCOMPRESSIBLE>(L, a) : step_t<LBM_F16S, LBM_QUASI_COMPRESSIBLE>(L, a);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename S, int KIND>
+static hipError_t calib_t(const Launch &L, const KArgs &a) {
+    if (L.off32)
+        hipLaunchKernelGGL((k_calib<S, KIND, uint32_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
+    else
+        hipLaunchKernelGGL((k_calib<S, KIND, uint64_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_calib(const Launch &L, int kind, int storage, const void *src, void *dst) {
+    if (L.n_tiles == 0) return hipSuccess;
+    Phys P{};
+    const KArgs a = make_args(L, P, src, dst);
+    if (storage == LBM_F64) return kind == 1 ? calib_t<double, 1>(L, a) : calib_t<double, 2>(L, a);
+    if (storage == LBM_F32) return kind == 1 ? calib_t<float, 1>(L, a) : calib_t<float, 2>(L, a);
+    return kind == 1 ? calib_t<_Float16, 1>(L, a) : calib_t<_Float16, 2>(L, a);
+}
+
+hipError_t launch_init(const Launch &L, const Phys &P, void *a_buf, void *b_buf, double ux, double uy, double uz) {
+    if (L.n_tiles == 0) return hipSuccess;
+    const KArgs a = make_args(L, P, nullptr, a_buf);
+    char *b = reinterpret_cast<char *>(b_buf);
+    switch (P.storage) {
+    case LBM_F64: hipLaunchKernelGGL(k_init<LBM_F64>, dim3(L.grid), block_of(L), 0, L.stream, a, b, ux, uy, uz); break;
+    case LBM_F32: hipLaunchKernelGGL(k_init<LBM_F32>, dim3(L.grid), block_of(L), 0, L.stream, a, b, ux, uy, uz); break;
+    default: hipLaunchKernelGGL(k_init<LBM_F16S>, dim3(L.grid), block_of(L), 0, L.stream, a, b, ux, uy, uz); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(hipStream_t s, double *p, size_t n) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro(const Launch &L, const Phys &P, const void *state, double *rho, double *u, int nx, int ny,
+                        int nz, double *partials) {
+    if (L.n_tiles == 0) return hipSuccess;
+    const KArgs a = make_args(L, P, state, nullptr);
+    switch (P.storage) {
+    case LBM_F64: hipLaunchKernelGGL(k_macro<LBM_F64>, dim3(L.grid), block_of(L), 0, L.stream, a, rho, u, nx, ny, nz, partials); break;
+    case LBM_F32: hipLaunchKernelGGL(k_macro<LBM_F32>, dim3(L.grid), block_of(L), 0, L.stream, a, rho, u, nx, ny, nz, partials); break;
+    default: hipLaunchKernelGGL(k_macro<LBM_F16S>, dim3(L.grid), block_of(L), 0, L.stream, a, rho, u, nx, ny, nz, partials); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(hipStream_t s, const double *partials, int n_tiles, double *out) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, s, partials, n_tiles, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_state(const Launch &L, const Phys &P, const void *state, double *dense, int nx, int ny, int nz) {
+    if (L.n_tiles == 0) return hipSuccess;
+    const KArgs a = make_args(L, P, state, nullptr);
+    switch (P.storage) {
+    case LBM_F64: hipLaunchKernelGGL(k_get_state<LBM_F64>, dim3(L.grid), block_of(L), 0, L.stream, a, dense, nx, ny, nz); break;
+    case LBM_F32: hipLaunchKernelGGL(k_get_state<LBM_F32>, dim3(L.grid), block_of(L), 0, L.stream, a, dense, nx, ny, nz); break;
+    default: hipLaunchKernelGGL(k_get_state<LBM_F16S>, dim3(L.grid), block_of(L), 0, L.stream, a, dense, nx, ny, nz); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_set_state(const Launch &L, const Phys &P, const double *dense, void *state, int nx, int ny, int nz) {
+    if (L.n_tiles == 0) return hipSuccess;
+    const KArgs a = make_args(L, P, nullptr, state);
+    switch (P.storage) {
+    case LBM_F64: hipLaunchKernelGGL(k_set_state<LBM_F64>, dim3(L.grid), block_of(L), 0, L.stream, a, dense, nx, ny, nz); break;
+    case LBM_F32: hipLaunchKernelGGL(k_set_state<LBM_F32>, dim3(L.grid), block_of(L), 0, L.stream, a, dense, nx, ny, nz); break;
+    default: hipLaunchKernelGGL(k_set_state<LBM_F16S>, dim3(L.grid), block_of(L), 0, L.stream, a, dense, nx, ny, nz); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_force_to_tiles(const Launch &L, const Phys &P, const double *g, void *tile_buf, int nx, int ny, int nz) {
+    if (L.n_tiles == 0) return hipSuccess;
+    const KArgs a = make_args(L, P, nullptr, nullptr);
+    if (P.storage == LBM_F64)
+        hipLaunchKernelGGL(k_force_to_tiles<double>, dim3(L.grid), block_of(L), 0, L.stream, a, g,
+                           reinterpret_cast<double *>(tile_buf), nx, ny, nz);
+    else
+        hipLaunchKernelGGL(k_force_to_tiles<float>, dim3(L.grid), block_of(L), 0, L.stream, a, g,
+                           reinterpret_cast<float *>(tile_buf), nx, ny, nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles_to_dense(const Launch &L, const void *tile_buf, int ncomp, int dtype, double *dense, int nx,
+                                 int ny, int nz) {
+    if (L.n_tiles == 0) return hipSuccess;
+    Phys P{};
+    const KArgs a = make_args(L, P, nullptr, nullptr);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_tiles_to_dense<double>, dim3(L.grid), block_of(L), 0, L.stream, a,
+                           reinterpret_cast<const double *>(tile_buf), ncomp, dense, nx, ny, nz);
+    else
+        hipLaunchKernelGGL(k_tiles_to_dense<float>, dim3(L.grid), block_of(L), 0, L.stream, a,
+                           reinterpret_cast<const float *>(tile_buf), ncomp, dense, nx, ny, nz);
+    return hipGetLastError();
+}
+
+static AdjArgs make_adj(const Launch &L, const Phys &P, const void *s, const void *eta_in, void *out, double *grad) {
+    AdjArgs a;
+    a.s = reinterpret_cast<const char *>(s);
+    a.eta_in = reinterpret_cast<const char *>(eta_in);
+    a.out = reinterpret_cast<char *>(out);
+    a.grad = grad;
+    a.tb = L.tb;
+    a.n_tiles = L.n_tiles;
+    a.P = P;
+    return a;
+}
+
+hipError_t launch_adjoint_seed(const Launch &L, const Phys &P, const void *s_prev, void *eta, double *grad) {
+    if (L.n_tiles == 0) return hipSuccess;
+    const AdjArgs a = make_adj(L, P, s_prev, nullptr, eta, grad);
+    if (L.off32)
+        hipLaunchKernelGGL(k_adj_seed<uint32_t>, dim3(L.grid), block_of(L), 0, L.stream, a);
+    else
+        hipLaunchKernelGGL(k_adj_seed<uint64_t>, dim3(L.grid), block_of(L), 0, L.stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const Launch &L, const Phys &P, const void *s_prev2, const void *eta_in, void *eta_out,
+                               double *grad) {
+    if (L.n_tiles == 0) return hipSuccess;
+    const AdjArgs a = make_adj(L, P, s_prev2, eta_in, eta_out, grad);
+    if (L.off32)
+        hipLaunchKernelGGL(k_adj_step<uint32_t>, dim3(L.grid), block_of(L), 0, L.stream, a);
+    else
+        hipLaunchKernelGGL(k_adj_step<uint64_t>, dim3(L.grid), block_of(L), 0, L.stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_final(const Launch &L, const Phys &P, const void *eta_in, void *lambda_out) {
+    if (L.n_tiles == 0) return hipSuccess;
+    const AdjArgs a = make_adj(L, P, nullptr, eta_in, lambda_out, nullptr);
+    if (L.off32)
+        hipLaunchKernelGGL(k_adj_final<uint32_t>, dim3(L.grid), block_of(L), 0, L.stream, a);
+    else
+        hipLaunchKernelGGL(k_adj_final<uint64_t>, dim3(L.grid), block_of(L), 0, L.stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace tlbm

@@ -1,0 +1,69 @@
+"""The C ABI: the library loads, exports every declared entry point, and
+rejects invalid arguments before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1611_02445_amd import _abi
+from paper_1611_02445_amd.lattice import Tiling
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_matches_binding_list():
+    assert declared_functions() == sorted(_abi.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_abi.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert _abi.lib().lbm_version().decode().startswith("tiledlbm")
+
+
+def _params(**kw):
+    p = dict(tau=0.8, rho0=1.0, storage=0, model=0, f16_log2_scale=20, tiles_per_wg=0)
+    p.update(kw)
+    return _abi.Params(**p)
+
+
+@pytest.mark.parametrize("bad", [dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(rho0=0.0),
+                                 dict(storage=3), dict(model=2), dict(f16_log2_scale=31), dict(tiles_per_wg=3)])
+def test_parameter_validation(bad):
+    t = Tiling(np.zeros((8, 8, 8), np.uint8), 7)
+    sz = _abi.Sizes()
+    rc = _abi.lib().lbm_required_bytes(t._ptr, ctypes.byref(_params(**bad)), ctypes.byref(sz))
+    assert rc == -1
+    assert _abi.lib().lbm_last_error()
+    ctx = ctypes.c_void_p()
+    rc = _abi.lib().lbm_create(t._ptr, ctypes.byref(_params(**bad)), None, None, None, None, None, ctypes.byref(ctx))
+    assert rc == -1 and not ctx.value
+
+
+def test_required_bytes():
+    t = Tiling(np.zeros((8, 12, 16), np.uint8), 7)
+    assert t.n_tiles == 2 * 3 * 4
+    for storage, nd, na in ((0, 8, 8), (1, 4, 4), (2, 2, 4)):
+        sz = _abi.Sizes()
+        _abi.call("lbm_required_bytes", t._ptr, ctypes.byref(_params(storage=storage)), ctypes.byref(sz))
+        assert sz.state_bytes == 24 * 19 * 64 * nd
+        assert sz.adjoint_bytes == 24 * 19 * 64 * na
+        assert sz.force_bytes == 24 * 3 * 64 * na
+        assert sz.grad_force_bytes == 24 * 3 * 64 * 8
+        assert sz.dense_nodes == 8 * 12 * 16
+        assert sz.table_bytes >= 24 * (8 + 27 * 4 + 12)
+
+
+def test_null_arguments():
+    assert _abi.lib().lbm_build_tiles(None, 4, 4, 4, 0, None) == -1
+    assert _abi.lib().lbm_step(None, 1) == -1
+    assert _abi.lib().lbm_macroscopic(None, None, None, None) == -1
