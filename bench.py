@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Throughput of the fused tiled D3Q19 step on one MI355X.
+
+Workload: a 256^3 periodic box of randomly placed, overlapping solid spheres
+(radius uniform in [4, 12), seeded centres) added until the porosity is 0.4;
+FP64 storage and arithmetic, LBGK tau = 0.7, uniform body force g_x = 1e-6,
+4^3 tiles with all-solid tiles skipped.  A step is one fused
+collide-and-stream update of every fluid node (one kernel launch); the timed
+region holds exactly --steps steps with the lattice resident in HBM.
+
+Prints one JSON line: MFLUPS (million fluid-node updates per second), the
+roofline of the step kernel (algorithmic bytes per launch / average launch
+time, against 8 TB/s), the CPU oracle timed on a bounded sample of the same
+workload, permeability after the run, and the FP32 / FP16-shifted storage
+variants with their errors against the FP64 result.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "MFLUPS + % HBM roofline, FP64 vs FP32/FP16 storage at stated error; adjoint MFLUPS"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = {"f64": 2 * 19 * 8, "f32": 2 * 19 * 4, "f16s": 2 * 19 * 2}
+PROFILE_DIR = os.path.join(HERE, "profiles")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "common.hpp", "kernels.hpp"):
+        with open(os.path.join(HERE, "paper_1611_02445_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel_tag, n_launch_units):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this
+    kernel (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or
+    None when there is none or the kernel source changed since it was taken."""
+    path = os.path.join(PROFILE_DIR, f"counters_{kernel_tag}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def build_case(args):
+    from paper_1611_02445_amd import inputs
+    t0 = time.time()
+    solid, n_sph = inputs.sphere_pack((args.n, args.n, args.n), args.porosity, 4.0, 12.0, seed=args.seed)
+    log(f"[bench] geometry {args.n}^3 spheres={n_sph} porosity={1 - solid.mean():.4f} ({time.time() - t0:.1f}s)")
+    return solid
+
+
+def time_storage(solid, storage, args, torch, want_state=False):
+    from paper_1611_02445_amd.lattice import Lattice
+    lat = Lattice(solid, args.tau, periodic=7, storage=storage, tiles_per_wg=args.tpw)
+    lat.init()
+    lat.set_force((args.g, 0.0, 0.0))
+    log(f"[bench] {storage}: tiles={lat.n_tiles} fluid={lat.n_fluid} eta_t={lat.tiling.eta_t:.4f}")
+    lat.step(args.warmup)
+    stream = lat.stream
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    lat.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    # per-launch spread (the paper times every launch separately)
+    nlaunch = min(100, args.steps)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nlaunch + 1)]
+    evs[0].record(stream)
+    for k in range(nlaunch):
+        lat.step(1)
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(nlaunch)])
+    steps_done = args.warmup + args.steps + nlaunch
+    k = lat.permeability(args.g)
+    _, _, sums = lat.macroscopic(fields=False)
+    out = dict(lat=lat, wall=wall, gpu_ms=gpu_ms, per=per, steps_done=steps_done, k=k, sums=sums)
+    if want_state:
+        out["u"] = lat.macroscopic()[1]
+    return out
+
+
+def time_calib(solid, args, torch):
+    """The paper's measurement kernels on the same tiles and launch shape."""
+    from paper_1611_02445_amd.lattice import Lattice
+    kind = 1 if args.kernel == "rw" else 2
+    lat = Lattice(solid, args.tau, periodic=7, storage="f64", tiles_per_wg=args.tpw)
+    lat.init()
+    a, b = lat.state_a, lat.state_b
+    for _ in range(args.warmup):
+        lat.calib_step(kind, a, b)
+        a, b = b, a
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(lat.stream)
+    for _ in range(args.steps):
+        lat.calib_step(kind, a, b)
+        a, b = b, a
+    ev1.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    nf = lat.n_fluid
+    gbs = BYTES_PER_UPDATE["f64"] * nf / (ms / 1e3) / 1e9
+    log(f"[bench] {args.kernel}-only: {nf / (ms / 1e3) / 1e6:.1f} MFLUPS, {ms * 1e3:.1f} us, {gbs:.0f} GB/s")
+    return {"kernel": args.kernel, "ms_per_launch": ms, "MFLUPS": nf / (ms / 1e3) / 1e6, "GBs": gbs,
+            "frac": gbs / HBM_PEAK_GBS, "fluid_nodes": nf, "tiles": lat.n_tiles}
+
+
+def cpu_baseline(solid, args):
+    """The oracle as it stands, on the same geometry, for a bounded number of
+    steps (about --cpu-seconds of CPU work)."""
+    import oracle as O
+    from oracle import tiles_ref
+    sp = tiles_ref.pad(solid, 7)
+    f = O.init(sp)
+    scratch = np.zeros_like(f)
+    nf = int((sp == 0).sum())
+    O.step(f[:, :4, :4, :4], sp[:4, :4, :4], args.tau)  # load + build
+    steps, t_used = 0, 0.0
+    while t_used < args.cpu_seconds and steps < 200:
+        t0 = time.perf_counter()
+        f = O.step(f, sp, args.tau, force=[args.g, 0.0, 0.0], periodic=7)
+        t_used += time.perf_counter() - t0
+        steps += 1
+    del scratch
+    return dict(value=nf * steps / t_used / 1e6, unit="MFLUPS", cores=O.num_threads(), kind="oracle",
+                sample=f"{steps} dense FP64 steps of the same {args.n}^3 sphere pack ({nf} fluid nodes), "
+                       f"{t_used:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256, help="box edge (nodes)")
+    ap.add_argument("--porosity", type=float, default=0.4)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--tau", type=float, default=0.7)
+    ap.add_argument("--g", type=float, default=1e-6)
+    ap.add_argument("--tpw", type=int, default=0, help="tiles per workgroup (0 = library default)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default="f32,f16s", help="extra storage variants ('' for none)")
+    ap.add_argument("--kernel", default="step", choices=["step", "rw", "prop"],
+                    help="time the fused step, or the paper's read/write-only (rw) or propagation-only (prop) kernel")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.copy_calib:
+        n = args.copy_calib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes": n * 8, "launches": 5}), flush=True)
+        return
+    solid = build_case(args)
+    if args.kernel != "step":
+        print(json.dumps(time_calib(solid, args, torch)), flush=True)
+        return
+
+    r = time_storage(solid, "f64", args, torch, want_state=bool(args.variants))
+    lat = r["lat"]
+    nf = lat.n_fluid
+    ms_per_step = r["gpu_ms"] / args.steps
+    mflups = nf * args.steps / (r["gpu_ms"] / 1e3) / 1e6
+    launch_s = ms_per_step / 1e3
+    alg_bytes = BYTES_PER_UPDATE["f64"] * nf
+    achieved = alg_bytes / launch_s / 1e9
+    traffic = counter_traffic("step_f64_spheres256", nf)
+    log(f"[bench] f64: {mflups:.1f} MFLUPS, {ms_per_step * 1e3:.1f} us/step, {achieved:.0f} GB/s algorithmic")
+
+    result = {
+        "metric": METRIC,
+        "value": round(mflups, 2),
+        "unit": "MFLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"random overlapping sphere pack {args.n}^3 periodic, porosity {args.porosity}, "
+                        f"radius U[4,12), seed {args.seed}; D3Q19 LBGK quasi-compressible, tau {args.tau}, "
+                        f"g_x {args.g}, 4^3 tiles, all-solid tiles skipped",
+            "box": [args.n, args.n, args.n],
+            "tiles": lat.n_tiles,
+            "fluid_nodes": nf,
+            "eta_t": round(lat.tiling.eta_t, 6),
+            "storage": "f64",
+            "workgroups": lat.info()["grid_blocks"],
+            "tiles_per_workgroup": -(-lat.n_tiles // lat.info()["grid_blocks"]),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic / launch_s / 1e9, 1),
+            "kernel": "k_step<f64, quasi-compressible>",
+            "bytes_per_fluid_update": BYTES_PER_UPDATE["f64"],
+        },
+        "launch_ms": {"min": round(float(r["per"].min()), 4), "mean": round(float(r["per"].mean()), 4),
+                      "max": round(float(r["per"].max()), 4)},
+        "wall_ms_per_step": round(r["wall"] * 1e3 / args.steps, 6),
+        "permeability": r["k"],
+        "steps_total": r["steps_done"],
+        "mass": r["sums"][0],
+    }
+    if traffic is not None:
+        result["roofline"]["traffic_bytes_per_fluid_update"] = round(traffic / nf, 1)
+
+    variants = {}
+    for st in [v for v in args.variants.split(",") if v]:
+        rv = time_storage(solid, st, args, torch, want_state=True)
+        ms = rv["gpu_ms"] / args.steps
+        mf = nf * args.steps / (rv["gpu_ms"] / 1e3) / 1e6
+        u64, uv = r["u"], rv["u"]
+        du = torch.linalg.vector_norm(uv - u64).item() / torch.linalg.vector_norm(u64).item()
+        dk = abs(rv["k"] - r["k"]) / abs(r["k"])
+        variants[st] = {"MFLUPS": round(mf, 2), "ms_per_step": round(ms, 6),
+                        "gain_over_f64": round(mf / mflups, 3),
+                        "hbm_frac": round(BYTES_PER_UPDATE[st] * nf / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "bytes_per_fluid_update": BYTES_PER_UPDATE[st],
+                        "rel_l2_velocity_vs_f64": du, "rel_permeability_err_vs_f64": dk,
+                        "mass_drift": (rv["sums"][0] - r["sums"][0]) / r["sums"][0]}
+        log(f"[bench] {st}: {mf:.1f} MFLUPS (x{mf / mflups:.2f}), |du|/|u| {du:.2e}, dk/k {dk:.2e}")
+        del rv
+    if variants:
+        result["variants"] = variants
+    del r, lat
+    torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(solid, args)
+        log(f"[bench] cpu baseline {result['cpu_baseline']['value']:.2f} MFLUPS on {result['cpu_baseline']['cores']} threads")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

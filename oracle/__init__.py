@@ -45,6 +45,7 @@ def lib():
         L = ctypes.CDLL(LIB)
         P = ctypes.c_void_p
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_lattice.argtypes = [P, P, P]
         L.oracle_feq.argtypes = [i32, f64, P, P]
         L.oracle_guo.argtypes = [f64, P, P, P]
@@ -75,6 +76,10 @@ def _f64(a):
 
 def _u8(a):
     return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def num_threads():
+    return int(lib().oracle_num_threads())
 
 
 def lattice():

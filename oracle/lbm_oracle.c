@@ -30,8 +30,20 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q 19
+
+/* threads the OpenMP loops use (1 without OpenMP) */
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* D3Q19 velocities.  0 = rest; 1..6 axis directions E N W S T B (e_3 = W =
  * (-1,0,0) as the Fig. 1 caption fixes); 7..18 the twelve edge directions. */

@@ -267,6 +267,31 @@ __device__ __forceinline__ void load_force(const Phys &P, int t, int lane, T &Fx
 // ---------------------------------------------------------------------------
 // the fused step (Alg. 2): gather with bounce-back, collide, store
 // ---------------------------------------------------------------------------
+// Lanes of every 128-byte cache line of a data block (16 FP64, 32 FP32 or
+// 64 FP16 values) that holds at least one fluid node.  All of these lanes
+// store -- solid ones a zero that is never read -- so that every line written
+// is written whole; a line of solid nodes only is neither read nor written.
+template <typename S>
+__device__ __forceinline__ uint64_t line_cover(uint64_t own) {
+    constexpr int L = 128 / (int)sizeof(S);
+    if constexpr (L >= 64) {
+        return own ? ~0ull : 0ull;
+    } else {
+        constexpr uint64_t G = (1ull << L) - 1;
+        uint64_t c = 0;
+#pragma unroll
+        for (int g = 0; g < 64 / L; ++g)
+            if ((own >> (g * L)) & G) c |= G << (g * L);
+        return c;
+    }
+}
+
+// the output lattice is not read again by this launch: stream it past the caches
+template <typename S>
+__device__ __forceinline__ void store_stream(S *p, S v) {
+    __builtin_nontemporal_store(v, p);
+}
+
 template <int ST, int MODEL, typename OffT>
 __global__ __launch_bounds__(512) void k_step(KArgs a) {
     using C = Codec<ST>;
@@ -276,20 +301,24 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const uint64_t own = a.tb.mask[t];
-    if (!lane_on(own)) return;  // solid nodes neither read nor write
-    Nbhd h;
-    load_nbhd(h, a.tb, t);
-    S raw[Q];
-    gather_all<false, S, OffT>(raw, h, a.src, t, lane);
+    const bool fl = lane_on(own);
     T d[Q];
+    if (fl) {  // solid nodes neither gather nor collide
+        Nbhd h;
+        load_nbhd(h, a.tb, t);
+        S raw[Q];
+        gather_all<false, S, OffT>(raw, h, a.src, t, lane);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = C::dec(raw[i], a.P.inv_scale);
-    T Fx, Fy, Fz;
-    load_force<T>(a.P, t, lane, Fx, Fy, Fz);
-    collide<T, MODEL>(d, T(a.P.rho_base), T(a.P.omega), T(a.P.kg), Fx, Fy, Fz);
-    S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + lane;
+        for (int i = 0; i < Q; ++i) d[i] = C::dec(raw[i], a.P.inv_scale);
+        T Fx, Fy, Fz;
+        load_force<T>(a.P, t, lane, Fx, Fy, Fz);
+        collide<T, MODEL>(d, T(a.P.rho_base), T(a.P.omega), T(a.P.kg), Fx, Fy, Fz);
+    }
+    if (lane_on(line_cover<S>(own))) {
+        S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + lane;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) out[i * TILE] = C::enc(d[i], a.P.scale);
+        for (int i = 0; i < Q; ++i) store_stream(out + i * TILE, fl ? C::enc(d[i], a.P.scale) : S(0));
+    }
 }
 
 // the paper's measurement kernels (Section 4.1): kind 1 "read/write only",
@@ -300,20 +329,24 @@ __global__ __launch_bounds__(512) void k_calib(KArgs a) {
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const uint64_t own = a.tb.mask[t];
-    if (!lane_on(own)) return;
+    const bool fl = lane_on(own);
     S v[Q];
-    if constexpr (KIND == 1) {
-        const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + lane;
+    if (fl) {
+        if constexpr (KIND == 1) {
+            const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + lane;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) v[i] = in[i * TILE];
-    } else {
-        Nbhd h;
-        load_nbhd(h, a.tb, t);
-        gather_all<false, S, OffT>(v, h, a.src, t, lane);
+            for (int i = 0; i < Q; ++i) v[i] = in[i * TILE];
+        } else {
+            Nbhd h;
+            load_nbhd(h, a.tb, t);
+            gather_all<false, S, OffT>(v, h, a.src, t, lane);
+        }
     }
-    S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + lane;
+    if (lane_on(line_cover<S>(own))) {
+        S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + lane;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) out[i * TILE] = v[i];
+        for (int i = 0; i < Q; ++i) store_stream(out + i * TILE, fl ? v[i] : S(0));
+    }
 }
 
 // ---------------------------------------------------------------------------
