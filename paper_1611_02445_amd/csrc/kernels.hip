@@ -1,17 +1,28 @@
 // gfx950 kernels of the tiled D3Q19 lattice-Boltzmann method.
 //
-// Mapping (re-designed for CDNA4 from the paper's Section 3.1 thread mapping):
-// one 4x4x4 tile = one wave64, lane n = x + 4y + 16z.  A lattice is stored
-// per tile as 19 contiguous blocks of 64 values ("data block", Section 3.2),
-// so the wave reads and writes its own node values as whole 64-lane vectors.
+// Mapping (re-designed for CDNA4 from the paper's thread mapping, Section 3.1):
+// one 4x4x4 tile = one wave64, lane n = x + 4y + 16z.  A lattice is stored per
+// tile as 19 blocks of 64 slots ("data block", Section 3.2).
+//
+// Slot order inside a block.  With FP64 and FP32 storage the tile's fluid
+// nodes are packed into the leading slots in node order (slot = number of
+// fluid nodes of the tile with a smaller node index), so a block of k fluid
+// nodes occupies ceil(k/L) 128-byte lines (L = 16 FP64 or 32 FP32 values)
+// instead of every line that holds one fluid node.  With FP16 storage a block
+// is exactly one 128-byte line and slot = node index.  This replaces the
+// paper's per-direction node maps (Eq. 11-13), tuned for 32-byte Kepler
+// sectors: at 128-byte lines what matters is how many lines a block touches.
 //
 // Streaming is a pull (gather) fused with collision (Section 2.4, Alg. 2).
-// For every direction the wave combines, on the scalar unit, the 64-bit fluid
-// masks of the tile and of the neighbours the direction reaches into a single
-// 64-bit "source is fluid" mask; that mask is then used directly as the lane
-// condition (inverse ballot) selecting between the upstream value and the
-// bounce-back value at the node itself.  Neighbour tile numbers come from the
-// 27-entry row of the tiling table (the 3x3x3 window of the tile map).
+// For every direction the lanes split into at most four regions by which
+// neighbour tile holds their source node; inside a region the source node is
+// this lane's index plus a constant, so its slot is
+//     slot = mbcnt(mask of that tile, shifted by the constant) + constant'
+// (one v_mbcnt pair) and every tile number, shift and constant is computed
+// once per wave on the scalar unit.  The scalar unit also combines the fluid
+// masks into one 64-bit "source is fluid" mask per direction, used directly
+// as the lane condition (inverse ballot) between the upstream value and the
+// halfway bounce-back value at the node itself.
 #include <hip/hip_runtime.h>
 
 #include <utility>
@@ -33,18 +44,21 @@ template <int ST> struct Codec;
 template <> struct Codec<LBM_F64> {
     using S = double;
     using T = double;
+    static constexpr bool PACKED = true;
     static __device__ __forceinline__ T dec(S v, float) { return v; }
     static __device__ __forceinline__ S enc(T v, float) { return v; }
 };
 template <> struct Codec<LBM_F32> {
     using S = float;
     using T = float;
+    static constexpr bool PACKED = true;
     static __device__ __forceinline__ T dec(S v, float) { return v; }
     static __device__ __forceinline__ S enc(T v, float) { return v; }
 };
 template <> struct Codec<LBM_F16S> {
     using S = _Float16;
     using T = float;
+    static constexpr bool PACKED = false;
     static __device__ __forceinline__ T dec(S v, float inv_scale) { return (float)v * inv_scale; }
     static __device__ __forceinline__ S enc(T v, float scale) { return (_Float16)(v * scale); }
 };
@@ -69,6 +83,18 @@ __device__ __forceinline__ int wave_tile() {
 }
 
 __device__ __forceinline__ bool lane_on(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ int mbcnt(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// slot of this lane's node in its own tile
+template <bool PACKED>
+__device__ __forceinline__ int own_slot(uint64_t own, int lane) {
+    if constexpr (PACKED) return mbcnt(own);
+    else return lane;
+}
 
 // ---------------------------------------------------------------------------
 // neighbourhood of a tile (wave-uniform: lives in SGPRs)
@@ -102,20 +128,33 @@ constexpr uint64_t region_mask(int sx, int sy, int sz, int bx, int by, int bz) {
     return r;
 }
 
-// bits of the neighbour mask that the lanes of one region read
+// Region (BX,BY,BZ) of the source offset (SX,SY,SZ): its lanes read the
+// neighbour tile K at in-tile node lane + OFF.
 template <int SX, int SY, int SZ, int BX, int BY, int BZ>
-__device__ __forceinline__ uint64_t region_fluid(const Nbhd &h) {
-    if constexpr ((BX && !SX) || (BY && !SY) || (BZ && !SZ)) {
+struct Region {
+    static constexpr bool axes_ok = !((BX && !SX) || (BY && !SY) || (BZ && !SZ));
+    static constexpr uint64_t LANES = axes_ok ? region_mask(SX, SY, SZ, BX, BY, BZ) : 0ull;
+    static constexpr bool EXISTS = LANES != 0;
+    static constexpr int K = 13 + BX * SX + 3 * BY * SY + 9 * BZ * SZ;
+    static constexpr int OFF = SX + 4 * SY + 16 * SZ - 4 * BX * SX - 16 * BY * SY - 64 * BZ * SZ;
+};
+
+// bits of the neighbour mask that one region's lanes read, aligned to lanes
+template <class R>
+__device__ __forceinline__ uint64_t region_source_bits(const Nbhd &h) {
+    if constexpr (!R::EXISTS) {
         return 0ull;
     } else {
-        constexpr uint64_t R = region_mask(SX, SY, SZ, BX, BY, BZ);
-        constexpr int k = 13 + BX * SX + 3 * BY * SY + 9 * BZ * SZ;
-        constexpr int off = SX + 4 * SY + 16 * SZ - 4 * BX * SX - 16 * BY * SY - 64 * BZ * SZ;
-        if constexpr (R == 0) return 0ull;
-        const uint64_t mk = h.m[k];
-        const uint64_t sh = off >= 0 ? (mk >> off) : (mk << (-off));
-        return sh & R;
+        const uint64_t mk = h.m[R::K];
+        return R::OFF >= 0 ? (mk >> R::OFF) : (mk << (-R::OFF));
     }
+}
+
+template <int SX, int SY, int SZ, int BX, int BY, int BZ>
+__device__ __forceinline__ uint64_t region_fluid(const Nbhd &h) {
+    using R = Region<SX, SY, SZ, BX, BY, BZ>;
+    if constexpr (!R::EXISTS) return 0ull;
+    else return region_source_bits<R>(h) & R::LANES;
 }
 
 // 64-bit mask: bit n set when lane n's source node exists and is fluid
@@ -127,77 +166,112 @@ __device__ __forceinline__ uint64_t source_fluid(const Nbhd &h) {
            region_fluid<SX, SY, SZ, 0, 1, 1>(h) | region_fluid<SX, SY, SZ, 1, 1, 1>(h);
 }
 
-template <int SX, int SY, int SZ, int BX, int BY, int BZ>
-__device__ __forceinline__ int region_tile(const Nbhd &h, int tile) {
-    if constexpr ((BX && !SX) || (BY && !SY) || (BZ && !SZ) || (!BX && !BY && !BZ)) {
-        return tile;
+// Element index (within the lattice) of direction I's value at this lane's
+// source node, for the lanes of one region:
+//   plain : (tile K) * 19 * 64 + I * 64 + lane + OFF
+//   packed: (tile K) * 19 * 64 + I * 64 + mbcnt(m_K shifted by OFF) + c,
+//           c = popcount(m_K below OFF) when OFF > 0
+// Every term but the mbcnt is wave-uniform.
+template <class R, int I, bool PACKED, typename OffT>
+__device__ __forceinline__ OffT region_elem(const Nbhd &h, int lane) {
+    const OffT tile_base = (OffT)h.nb[R::K] * (OffT)(Q * TILE) + (OffT)(I * TILE);
+    if constexpr (PACKED) {
+        constexpr int POS = R::OFF > 0 ? R::OFF : 0;
+        const uint64_t mk = h.m[R::K];
+        const int c = POS ? __builtin_popcountll(mk & ((1ull << POS) - 1ull)) : 0;
+        return (OffT)mbcnt(region_source_bits<R>(h)) + (tile_base + (OffT)c);
     } else {
-        constexpr uint64_t R = region_mask(SX, SY, SZ, BX, BY, BZ);
-        constexpr int k = 13 + BX * SX + 3 * BY * SY + 9 * BZ * SZ;
-        return lane_on(R) ? h.nb[k] : tile;
+        return (OffT)lane + (tile_base + (OffT)R::OFF);
     }
 }
 
-// tile holding lane's source node (garbage where the source is outside)
-template <int SX, int SY, int SZ>
-__device__ __forceinline__ int source_tile(const Nbhd &h) {
-    int t = h.nb[13];
-    t = region_tile<SX, SY, SZ, 1, 0, 0>(h, t);
-    t = region_tile<SX, SY, SZ, 0, 1, 0>(h, t);
-    t = region_tile<SX, SY, SZ, 1, 1, 0>(h, t);
-    t = region_tile<SX, SY, SZ, 0, 0, 1>(h, t);
-    t = region_tile<SX, SY, SZ, 1, 0, 1>(h, t);
-    t = region_tile<SX, SY, SZ, 0, 1, 1>(h, t);
-    t = region_tile<SX, SY, SZ, 1, 1, 1>(h, t);
-    return t;
-}
-
-// lane index of the source node inside its tile (coordinates wrap mod 4)
-template <int SX, int SY, int SZ>
-__device__ __forceinline__ int source_lane(int lane) {
-    const int x = SX ? ((lane + SX) & 3) : (lane & 3);
-    const int y = SY ? ((lane + 4 * SY) & 12) : (lane & 12);
-    const int z = SZ ? ((lane + 16 * SZ) & 48) : (lane & 48);
-    return x | y | z;
+template <int SX, int SY, int SZ, int BX, int BY, int BZ, int I, bool PACKED, typename OffT>
+__device__ __forceinline__ OffT region_pick(const Nbhd &h, int lane, OffT cur) {
+    using R = Region<SX, SY, SZ, BX, BY, BZ>;
+    if constexpr (!R::EXISTS) return cur;
+    else return lane_on(R::LANES) ? region_elem<R, I, PACKED, OffT>(h, lane) : cur;
 }
 
 template <typename OffT, typename S>
-__device__ __forceinline__ S load_at(const char *base, OffT off) {
-    return *reinterpret_cast<const S *>(base + off);
+__device__ __forceinline__ S load_elem(const char *base, OffT elem) {
+    return *reinterpret_cast<const S *>(base + elem * (OffT)sizeof(S));
 }
 
 // Gather of direction I for this lane: the value of direction I at the source
 // node x - c_I (REV = false: pull streaming S) or x + c_I (REV = true: its
 // transpose S^T), or, when that node is solid or missing, the value of the
 // opposite direction at the node itself (halfway bounce-back).
-template <int I, bool REV, typename S, typename OffT>
-__device__ __forceinline__ S gather_one(const Nbhd &h, const char *base, int t, int lane) {
-    constexpr OffT TB = (OffT)(Q * TILE * sizeof(S));  // bytes per tile
+template <int I, bool REV, bool PACKED, typename S, typename OffT>
+__device__ __forceinline__ S gather_one(const Nbhd &h, const char *base, int t, int lane, int slot) {
+    const OffT self = (OffT)t * (OffT)(Q * TILE) + (OffT)slot;
     if constexpr (I == 0) {
-        return load_at<OffT, S>(base, (OffT)t * TB + (OffT)(lane * sizeof(S)));
+        return load_elem<OffT, S>(base, self);
     } else {
         constexpr int SX = REV ? CX[I] : -CX[I];
         constexpr int SY = REV ? CY[I] : -CY[I];
         constexpr int SZ = REV ? CZ[I] : -CZ[I];
         constexpr int OP = opposite(I);
         const uint64_t ok_mask = source_fluid<SX, SY, SZ>(h);
-        const int tile = source_tile<SX, SY, SZ>(h);
-        const int sn = source_lane<SX, SY, SZ>(lane);
-        const OffT o_pull = (OffT)tile * TB + (OffT)((I * TILE + sn) * (int)sizeof(S));
-        const OffT o_bb = (OffT)t * TB + (OffT)((OP * TILE + lane) * (int)sizeof(S));
-        return load_at<OffT, S>(base, lane_on(ok_mask) ? o_pull : o_bb);
+        OffT e = region_elem<Region<SX, SY, SZ, 0, 0, 0>, I, PACKED, OffT>(h, lane);
+        e = region_pick<SX, SY, SZ, 1, 0, 0, I, PACKED, OffT>(h, lane, e);
+        e = region_pick<SX, SY, SZ, 0, 1, 0, I, PACKED, OffT>(h, lane, e);
+        e = region_pick<SX, SY, SZ, 1, 1, 0, I, PACKED, OffT>(h, lane, e);
+        e = region_pick<SX, SY, SZ, 0, 0, 1, I, PACKED, OffT>(h, lane, e);
+        e = region_pick<SX, SY, SZ, 1, 0, 1, I, PACKED, OffT>(h, lane, e);
+        e = region_pick<SX, SY, SZ, 0, 1, 1, I, PACKED, OffT>(h, lane, e);
+        e = region_pick<SX, SY, SZ, 1, 1, 1, I, PACKED, OffT>(h, lane, e);
+        const OffT bb = self + (OffT)(OP * TILE);
+        return load_elem<OffT, S>(base, lane_on(ok_mask) ? e : bb);
     }
 }
 
-template <bool REV, typename S, typename OffT, int... Is>
+template <bool REV, bool PACKED, typename S, typename OffT, int... Is>
 __device__ __forceinline__ void gather_all_impl(S (&v)[Q], const Nbhd &h, const char *base, int t, int lane,
-                                                std::integer_sequence<int, Is...>) {
-    ((v[Is] = gather_one<Is, REV, S, OffT>(h, base, t, lane)), ...);
+                                                int slot, std::integer_sequence<int, Is...>) {
+    ((v[Is] = gather_one<Is, REV, PACKED, S, OffT>(h, base, t, lane, slot)), ...);
 }
 
-template <bool REV, typename S, typename OffT>
-__device__ __forceinline__ void gather_all(S (&v)[Q], const Nbhd &h, const char *base, int t, int lane) {
-    gather_all_impl<REV, S, OffT>(v, h, base, t, lane, std::make_integer_sequence<int, Q>{});
+template <bool REV, bool PACKED, typename S, typename OffT>
+__device__ __forceinline__ void gather_all(S (&v)[Q], const Nbhd &h, const char *base, int t, int lane, int slot) {
+    gather_all_impl<REV, PACKED, S, OffT>(v, h, base, t, lane, slot, std::make_integer_sequence<int, Q>{});
+}
+
+// ---------------------------------------------------------------------------
+// where each lane stores
+// ---------------------------------------------------------------------------
+// Every 128-byte line of a block that holds a fluid value is written whole:
+// lanes of solid nodes store a zero (never read) into the line's other slots,
+// lines without fluid values are neither read nor written.
+//   packed: fluid lane -> its slot; the j-th solid lane -> slot k + j while
+//           that is below k rounded up to a whole line (k = fluid nodes)
+//   plain : every lane of a line holding a fluid node, at slot = lane
+template <typename S, bool PACKED>
+__device__ __forceinline__ bool store_slot(uint64_t own, bool fl, int lane, int slot, int &where) {
+    constexpr int L = 128 / (int)sizeof(S);
+    if constexpr (PACKED) {
+        const int k = __builtin_popcountll(own);
+        const int top = (k + L - 1) / L * L;
+        where = fl ? slot : k + (lane - slot);
+        return where < top;
+    } else {
+        uint64_t cover = 0;
+        if constexpr (L >= 64) {
+            cover = own ? ~0ull : 0ull;
+        } else {
+            constexpr uint64_t G = (1ull << L) - 1;
+#pragma unroll
+            for (int g = 0; g < 64 / L; ++g)
+                if ((own >> (g * L)) & G) cover |= G << (g * L);
+        }
+        where = lane;
+        return lane_on(cover);
+    }
+}
+
+// the output lattice is not read again by this launch: stream it past the caches
+template <typename S>
+__device__ __forceinline__ void store_stream(S *p, S v) {
+    __builtin_nontemporal_store(v, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -250,6 +324,7 @@ struct KArgs {
     Phys P;
 };
 
+// the per-node force field is kept in plain lane order [tile][3][64]
 template <typename T>
 __device__ __forceinline__ void load_force(const Phys &P, int t, int lane, T &Fx, T &Fy, T &Fz) {
     if (P.field) {
@@ -267,55 +342,33 @@ __device__ __forceinline__ void load_force(const Phys &P, int t, int lane, T &Fx
 // ---------------------------------------------------------------------------
 // the fused step (Alg. 2): gather with bounce-back, collide, store
 // ---------------------------------------------------------------------------
-// Lanes of every 128-byte cache line of a data block (16 FP64, 32 FP32 or
-// 64 FP16 values) that holds at least one fluid node.  All of these lanes
-// store -- solid ones a zero that is never read -- so that every line written
-// is written whole; a line of solid nodes only is neither read nor written.
-template <typename S>
-__device__ __forceinline__ uint64_t line_cover(uint64_t own) {
-    constexpr int L = 128 / (int)sizeof(S);
-    if constexpr (L >= 64) {
-        return own ? ~0ull : 0ull;
-    } else {
-        constexpr uint64_t G = (1ull << L) - 1;
-        uint64_t c = 0;
-#pragma unroll
-        for (int g = 0; g < 64 / L; ++g)
-            if ((own >> (g * L)) & G) c |= G << (g * L);
-        return c;
-    }
-}
-
-// the output lattice is not read again by this launch: stream it past the caches
-template <typename S>
-__device__ __forceinline__ void store_stream(S *p, S v) {
-    __builtin_nontemporal_store(v, p);
-}
-
 template <int ST, int MODEL, typename OffT>
 __global__ __launch_bounds__(512) void k_step(KArgs a) {
     using C = Codec<ST>;
     using S = typename C::S;
     using T = typename C::T;
+    constexpr bool PK = C::PACKED;
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const uint64_t own = a.tb.mask[t];
     const bool fl = lane_on(own);
+    const int slot = own_slot<PK>(own, lane);
     T d[Q];
     if (fl) {  // solid nodes neither gather nor collide
         Nbhd h;
         load_nbhd(h, a.tb, t);
         S raw[Q];
-        gather_all<false, S, OffT>(raw, h, a.src, t, lane);
+        gather_all<false, PK, S, OffT>(raw, h, a.src, t, lane, slot);
 #pragma unroll
         for (int i = 0; i < Q; ++i) d[i] = C::dec(raw[i], a.P.inv_scale);
         T Fx, Fy, Fz;
         load_force<T>(a.P, t, lane, Fx, Fy, Fz);
         collide<T, MODEL>(d, T(a.P.rho_base), T(a.P.omega), T(a.P.kg), Fx, Fy, Fz);
     }
-    if (lane_on(line_cover<S>(own))) {
-        S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + lane;
+    int where;
+    if (store_slot<S, PK>(own, fl, lane, slot, where)) {
+        S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + where;
 #pragma unroll
         for (int i = 0; i < Q; ++i) store_stream(out + i * TILE, fl ? C::enc(d[i], a.P.scale) : S(0));
     }
@@ -323,34 +376,37 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
 
 // the paper's measurement kernels (Section 4.1): kind 1 "read/write only",
 // kind 2 "propagation only"
-template <typename S, int KIND, typename OffT>
+template <typename S, bool PK, int KIND, typename OffT>
 __global__ __launch_bounds__(512) void k_calib(KArgs a) {
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const uint64_t own = a.tb.mask[t];
     const bool fl = lane_on(own);
+    const int slot = own_slot<PK>(own, lane);
     S v[Q];
     if (fl) {
         if constexpr (KIND == 1) {
-            const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + lane;
+            const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + slot;
 #pragma unroll
             for (int i = 0; i < Q; ++i) v[i] = in[i * TILE];
         } else {
             Nbhd h;
             load_nbhd(h, a.tb, t);
-            gather_all<false, S, OffT>(v, h, a.src, t, lane);
+            gather_all<false, PK, S, OffT>(v, h, a.src, t, lane, slot);
         }
     }
-    if (lane_on(line_cover<S>(own))) {
-        S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + lane;
+    int where;
+    if (store_slot<S, PK>(own, fl, lane, slot, where)) {
+        S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + where;
 #pragma unroll
         for (int i = 0; i < Q; ++i) store_stream(out + i * TILE, fl ? v[i] : S(0));
     }
 }
 
 // ---------------------------------------------------------------------------
-// initial state: feq(rho0, u0) at fluid nodes of both lattices, 0 at solid
+// initial state: feq(rho0, u0) at every fluid slot of both lattices, 0 in all
+// other slots
 // ---------------------------------------------------------------------------
 template <int ST>
 __global__ __launch_bounds__(512) void k_init(KArgs a, char *b, double ux, double uy, double uz) {
@@ -358,8 +414,9 @@ __global__ __launch_bounds__(512) void k_init(KArgs a, char *b, double ux, doubl
     using S = typename C::S;
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
-    const int lane = (int)(threadIdx.x & 63);
-    const bool fl = (a.tb.mask[t] >> lane) & 1;
+    const int lane = (int)(threadIdx.x & 63);  // = slot here
+    const uint64_t own = a.tb.mask[t];
+    const bool used = C::PACKED ? lane < __builtin_popcountll(own) : (bool)((own >> lane) & 1);
     const double rho = a.P.rho0;
     const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
     S *pa = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + lane;
@@ -370,7 +427,7 @@ __global__ __launch_bounds__(512) void k_init(KArgs a, char *b, double ux, doubl
         const double P = 3.0 * cu + 4.5 * cu * cu - usq;
         const double feq = (a.P.model == LBM_QUASI_COMPRESSIBLE) ? weight(i) * rho * (1.0 + P) : weight(i) * (rho + P);
         const double dv = feq - weight(i) * a.P.rho_base;
-        const S v = fl ? C::enc((typename C::T)dv, a.P.scale) : S(0);
+        const S v = used ? C::enc((typename C::T)dv, a.P.scale) : S(0);
         pa[i * TILE] = v;
         pb[i * TILE] = v;
     }
@@ -410,16 +467,20 @@ __global__ __launch_bounds__(512) void k_macro(KArgs a, double *rho_out, double 
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const bool fl = (a.tb.mask[t] >> lane) & 1;
-    const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + lane;
+    const uint64_t own = a.tb.mask[t];
+    const bool fl = (own >> lane) & 1;
+    const int slot = own_slot<C::PACKED>(own, lane);
     double drho = 0, jx = 0, jy = 0, jz = 0;
+    if (fl) {
+        const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + slot;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const double v = (double)C::dec(in[i * TILE], a.P.inv_scale);
-        drho += v;
-        jx += CX[i] * v;
-        jy += CY[i] * v;
-        jz += CZ[i] * v;
+        for (int i = 0; i < Q; ++i) {
+            const double v = (double)C::dec(in[i * TILE], a.P.inv_scale);
+            drho += v;
+            jx += CX[i] * v;
+            jy += CY[i] * v;
+            jz += CZ[i] * v;
+        }
     }
     T Fx, Fy, Fz;
     load_force<T>(a.P, t, lane, Fx, Fy, Fz);
@@ -501,17 +562,19 @@ __global__ __launch_bounds__(512) void k_get_state(KArgs a, double *dense, int n
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const bool fl = (a.tb.mask[t] >> lane) & 1;
+    const uint64_t own = a.tb.mask[t];
+    if (!((own >> lane) & 1)) return;  // the dense array was zero-filled
+    const int slot = own_slot<C::PACKED>(own, lane);
     const size_t N = (size_t)nx * ny * nz;
     const size_t n = dense_index(a.tb.xyz + 4 * (size_t)t, lane, nx, ny);
-    const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + lane;
+    const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + slot;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const double v = (double)C::dec(in[i * TILE], a.P.inv_scale) + weight(i) * a.P.rho_base;
-        dense[(size_t)i * N + n] = fl ? v : 0.0;
-    }
+    for (int i = 0; i < Q; ++i)
+        dense[(size_t)i * N + n] = (double)C::dec(in[i * TILE], a.P.inv_scale) + weight(i) * a.P.rho_base;
 }
 
+// every slot is written once: fluid lanes their value at their slot, solid
+// lanes a zero at the slots left over
 template <int ST>
 __global__ __launch_bounds__(512) void k_set_state(KArgs a, const double *dense, int nx, int ny, int nz) {
     using C = Codec<ST>;
@@ -520,13 +583,16 @@ __global__ __launch_bounds__(512) void k_set_state(KArgs a, const double *dense,
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const bool fl = (a.tb.mask[t] >> lane) & 1;
+    const uint64_t own = a.tb.mask[t];
+    const bool fl = (own >> lane) & 1;
+    const int slot = own_slot<C::PACKED>(own, lane);
+    const int where = fl ? slot : (C::PACKED ? __builtin_popcountll(own) + (lane - slot) : lane);
     const size_t N = (size_t)nx * ny * nz;
     const size_t n = dense_index(a.tb.xyz + 4 * (size_t)t, lane, nx, ny);
-    S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + lane;
+    S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + where;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const double v = dense[(size_t)i * N + n] - weight(i) * a.P.rho_base;
+        const double v = fl ? dense[(size_t)i * N + n] - weight(i) * a.P.rho_base : 0.0;
         out[i * TILE] = fl ? C::enc((T)v, a.P.scale) : S(0);
     }
 }
@@ -557,7 +623,7 @@ __global__ __launch_bounds__(512) void k_tiles_to_dense(KArgs a, const T *in, in
 }
 
 // ---------------------------------------------------------------------------
-// discrete adjoint (quasi-compressible, FP64)
+// discrete adjoint (quasi-compressible, FP64, packed slots)
 //
 // For the local collision C(g, F) with rho = sum g, u = (sum c g + F/2)/rho:
 //   (J^T lam)_j = (1 - 1/tau) lam_j + A + V.(c_j - u)/rho
@@ -621,11 +687,20 @@ struct AdjArgs {
     const char *s;      // forward lattice feeding the forward gather
     const char *eta_in; // adjoint lattice feeding the reverse gather
     char *out;          // adjoint lattice written
-    double *grad;       // [n_tiles][3][64] FP64, dL/dg
+    double *grad;       // [n_tiles][3][64] FP64 (lane order), dL/dg
     DevTables tb;
     int n_tiles;
     Phys P;
 };
+
+__device__ __forceinline__ void store_adjoint(double *tile_out, uint64_t own, bool fl, int lane, int slot,
+                                              const double (&v)[Q]) {
+    int where;
+    if (store_slot<double, true>(own, fl, lane, slot, where)) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) tile_out[i * TILE + where] = fl ? v[i] : 0.0;
+    }
+}
 
 // seed: from s_{T-1}: g_T = S s_{T-1}, s_T = C(g_T), lam_T = dL/ds_T,
 // eta_T = J_T^T lam_T, grad = rho0 [(dC/dF)^T lam_T + dL/dF]
@@ -634,44 +709,40 @@ __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    double *eo = reinterpret_cast<double *>(a.out) + (size_t)t * Q * TILE + lane;
-    double *go = a.grad + (size_t)t * 3 * TILE + lane;
     const uint64_t own = a.tb.mask[t];
-    if (!lane_on(own)) {
+    const bool fl = lane_on(own);
+    const int slot = own_slot<true>(own, lane);
+    double eta[Q], gx = 0, gy = 0, gz = 0;
+    if (fl) {
+        Nbhd h;
+        load_nbhd(h, a.tb, t);
+        double g[Q];
+        gather_all<false, true, double, OffT>(g, h, a.s, t, lane, slot);
+        double Fx, Fy, Fz;
+        load_force<double>(a.P, t, lane, Fx, Fy, Fz);
+        double s[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) eo[i * TILE] = 0.0;
-        go[0] = go[TILE] = go[2 * TILE] = 0.0;
-        return;
+        for (int i = 0; i < Q; ++i) s[i] = g[i];
+        collide<double, LBM_QUASI_COMPRESSIBLE>(s, 0.0, a.P.omega, a.P.kg, Fx, Fy, Fz);
+        double rT = 0, jx = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            rT += s[i];
+            jx += CX[i] * s[i];
+        }
+        const double irT = 1.0 / rT;
+        const double uxT = (jx - 0.5 * Fx) * irT;
+        double lam[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lam[i] = (CX[i] - uxT) * irT * a.P.inv_nfluid;
+        collide_jt(g, lam, a.P.omega, a.P.kg, Fx, Fy, Fz, eta, gx, gy, gz);
+        gx += -0.5 * irT * a.P.inv_nfluid;
     }
-    Nbhd h;
-    load_nbhd(h, a.tb, t);
-    double g[Q];
-    gather_all<false, double, OffT>(g, h, a.s, t, lane);
-    double Fx, Fy, Fz;
-    load_force<double>(a.P, t, lane, Fx, Fy, Fz);
-    double s[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) s[i] = g[i];
-    collide<double, LBM_QUASI_COMPRESSIBLE>(s, 0.0, a.P.omega, a.P.kg, Fx, Fy, Fz);
-    double rT = 0, jx = 0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        rT += s[i];
-        jx += CX[i] * s[i];
-    }
-    const double irT = 1.0 / rT;
-    const double uxT = (jx - 0.5 * Fx) * irT;
-    double lam[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) lam[i] = (CX[i] - uxT) * irT * a.P.inv_nfluid;
-    double eta[Q], gx, gy, gz;
-    collide_jt(g, lam, a.P.omega, a.P.kg, Fx, Fy, Fz, eta, gx, gy, gz);
-    gx += -0.5 * irT * a.P.inv_nfluid;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) eo[i * TILE] = eta[i];
-    go[0] = a.P.rho0 * gx;
-    go[TILE] = a.P.rho0 * gy;
-    go[2 * TILE] = a.P.rho0 * gz;
+    store_adjoint(reinterpret_cast<double *>(a.out) + (size_t)t * Q * TILE, own, fl, lane, slot, eta);
+    double *go = a.grad + (size_t)t * 3 * TILE + lane;
+    go[0] = fl ? a.P.rho0 * gx : 0.0;
+    go[TILE] = fl ? a.P.rho0 * gy : 0.0;
+    go[2 * TILE] = fl ? a.P.rho0 * gz : 0.0;
 }
 
 // step: lam_{t-1} = S^T eta_t (reverse gather), g_{t-1} = S s_{t-2},
@@ -681,28 +752,26 @@ __global__ __launch_bounds__(512) void k_adj_step(AdjArgs a) {
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    double *eo = reinterpret_cast<double *>(a.out) + (size_t)t * Q * TILE + lane;
     const uint64_t own = a.tb.mask[t];
-    if (!lane_on(own)) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) eo[i * TILE] = 0.0;
-        return;
+    const bool fl = lane_on(own);
+    const int slot = own_slot<true>(own, lane);
+    double eta[Q];
+    if (fl) {
+        Nbhd h;
+        load_nbhd(h, a.tb, t);
+        double lam[Q], g[Q];
+        gather_all<true, true, double, OffT>(lam, h, a.eta_in, t, lane, slot);
+        gather_all<false, true, double, OffT>(g, h, a.s, t, lane, slot);
+        double Fx, Fy, Fz;
+        load_force<double>(a.P, t, lane, Fx, Fy, Fz);
+        double gx, gy, gz;
+        collide_jt(g, lam, a.P.omega, a.P.kg, Fx, Fy, Fz, eta, gx, gy, gz);
+        double *go = a.grad + (size_t)t * 3 * TILE + lane;
+        go[0] += a.P.rho0 * gx;
+        go[TILE] += a.P.rho0 * gy;
+        go[2 * TILE] += a.P.rho0 * gz;
     }
-    Nbhd h;
-    load_nbhd(h, a.tb, t);
-    double lam[Q], g[Q];
-    gather_all<true, double, OffT>(lam, h, a.eta_in, t, lane);
-    gather_all<false, double, OffT>(g, h, a.s, t, lane);
-    double Fx, Fy, Fz;
-    load_force<double>(a.P, t, lane, Fx, Fy, Fz);
-    double eta[Q], gx, gy, gz;
-    collide_jt(g, lam, a.P.omega, a.P.kg, Fx, Fy, Fz, eta, gx, gy, gz);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) eo[i * TILE] = eta[i];
-    double *go = a.grad + (size_t)t * 3 * TILE + lane;
-    go[0] += a.P.rho0 * gx;
-    go[TILE] += a.P.rho0 * gy;
-    go[2 * TILE] += a.P.rho0 * gz;
+    store_adjoint(reinterpret_cast<double *>(a.out) + (size_t)t * Q * TILE, own, fl, lane, slot, eta);
 }
 
 // final: lam_0 = S^T eta_1
@@ -711,19 +780,16 @@ __global__ __launch_bounds__(512) void k_adj_final(AdjArgs a) {
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    double *lo = reinterpret_cast<double *>(a.out) + (size_t)t * Q * TILE + lane;
     const uint64_t own = a.tb.mask[t];
-    if (!lane_on(own)) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) lo[i * TILE] = 0.0;
-        return;
-    }
-    Nbhd h;
-    load_nbhd(h, a.tb, t);
+    const bool fl = lane_on(own);
+    const int slot = own_slot<true>(own, lane);
     double lam[Q];
-    gather_all<true, double, OffT>(lam, h, a.eta_in, t, lane);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) lo[i * TILE] = lam[i];
+    if (fl) {
+        Nbhd h;
+        load_nbhd(h, a.tb, t);
+        gather_all<true, true, double, OffT>(lam, h, a.eta_in, t, lane, slot);
+    }
+    store_adjoint(reinterpret_cast<double *>(a.out) + (size_t)t * Q * TILE, own, fl, lane, slot, lam);
 }
 
 // ---------------------------------------------------------------------------
@@ -762,12 +828,13 @@ hipError_t launch_step(const Launch &L, const Phys &P, const void *src, void *ds
     return hipErrorInvalidValue;
 }
 
-template <typename S, int KIND>
+template <int ST, int KIND>
 static hipError_t calib_t(const Launch &L, const KArgs &a) {
+    using C = Codec<ST>;
     if (L.off32)
-        hipLaunchKernelGGL((k_calib<S, KIND, uint32_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
+        hipLaunchKernelGGL((k_calib<typename C::S, C::PACKED, KIND, uint32_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
     else
-        hipLaunchKernelGGL((k_calib<S, KIND, uint64_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
+        hipLaunchKernelGGL((k_calib<typename C::S, C::PACKED, KIND, uint64_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
     return hipGetLastError();
 }
 
@@ -775,9 +842,9 @@ hipError_t launch_calib(const Launch &L, int kind, int storage, const void *src,
     if (L.n_tiles == 0) return hipSuccess;
     Phys P{};
     const KArgs a = make_args(L, P, src, dst);
-    if (storage == LBM_F64) return kind == 1 ? calib_t<double, 1>(L, a) : calib_t<double, 2>(L, a);
-    if (storage == LBM_F32) return kind == 1 ? calib_t<float, 1>(L, a) : calib_t<float, 2>(L, a);
-    return kind == 1 ? calib_t<_Float16, 1>(L, a) : calib_t<_Float16, 2>(L, a);
+    if (storage == LBM_F64) return kind == 1 ? calib_t<LBM_F64, 1>(L, a) : calib_t<LBM_F64, 2>(L, a);
+    if (storage == LBM_F32) return kind == 1 ? calib_t<LBM_F32, 1>(L, a) : calib_t<LBM_F32, 2>(L, a);
+    return kind == 1 ? calib_t<LBM_F16S, 1>(L, a) : calib_t<LBM_F16S, 2>(L, a);
 }
 
 hipError_t launch_init(const Launch &L, const Phys &P, void *a_buf, void *b_buf, double ux, double uy, double uz) {
