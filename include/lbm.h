@@ -160,8 +160,10 @@ int lbm_current_state(lbm_ctx *ctx, void **state);
  * i.e. the velocity the last collision used.
  *   rho_dev  device FP64 [nz][ny][nx] or NULL; 0 at solid and dropped nodes
  *   u_dev    device FP64 [3][nz][ny][nx] or NULL
- *   sums     host double[8]: total mass, momentum x/y/z, fluid node count,
- *            max |u|, number of fluid nodes with a non-finite rho or u, 0.
+ *   sums     host double[8]: total mass sum rho, momentum sum rho u (x, y, z),
+ *            fluid node count, max |u|, number of fluid nodes with a
+ *            non-finite rho or u, and sum u_x (the adjoint's loss is
+ *            sums[7] / sums[4], the mean x-velocity over fluid nodes).
  *            Reduced in FP64 in a fixed order (bitwise reproducible).
  * Synchronises the stream.  Returns LBM_E_NUMERIC (after filling sums) when a
  * non-finite value was found. */

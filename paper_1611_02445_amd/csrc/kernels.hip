@@ -510,6 +510,7 @@ __global__ __launch_bounds__(512) void k_macro(KArgs a, double *rho_out, double 
     const double s4 = wave_sum(fl ? 1.0 : 0.0);
     const double s5 = wave_max(fl && finite ? sqrt(ux * ux + uy * uy + uz * uz) : 0.0);
     const double s6 = wave_sum(fl && !finite ? 1.0 : 0.0);
+    const double s7 = wave_sum(fl ? ux : 0.0);
     if (lane == 0) {
         double *p = partials + (size_t)t * NSUM;
         p[0] = s0;
@@ -519,7 +520,7 @@ __global__ __launch_bounds__(512) void k_macro(KArgs a, double *rho_out, double 
         p[4] = s4;
         p[5] = s5;
         p[6] = s6;
-        p[7] = 0.0;
+        p[7] = s7;
     }
 }
 
