@@ -99,6 +99,10 @@ typedef struct lbm_params {
     int32_t model;          /* lbm_model: Eq. 3+5 (0) or Eq. 4+6 (1) */
     int32_t f16_log2_scale; /* LBM_F16S: stored h = fp16(2^k (f_i - w_i rho0)), k in [0, 30] */
     int32_t tiles_per_wg;   /* tiles (wave64s) per workgroup: 1, 2, 4 or 8; 0 = default */
+    int32_t f16_rounding;   /* LBM_F16S stores: 0 = stochastic (unbiased; default), 1 = nearest-even.
+                               Stochastic rounding draws its bits from a counter-based hash of
+                               (tile, node, direction, launch counter): results are reproducible
+                               for the same sequence of launches on the context. */
 } lbm_params;
 
 typedef struct lbm_sizes {
@@ -125,7 +129,7 @@ int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *params, lbm_siz
  * The tables are copied to the device and the stream is synchronised before
  * returning, so `tiles` may be freed afterwards.  Parameters are validated:
  * tau > 1/2, known storage and model, f16 scale in [0,30], tiles_per_wg in
- * {0,1,2,4,8}; the tables are checked (every neighbour index in [-1, n_tiles),
+ * {0,1,2,4,8}, f16_rounding in {0,1}; the tables are checked (every neighbour index in [-1, n_tiles),
  * no empty kept tile). */
 int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void *state_a, void *state_b,
                void *tables, void *scratch, void *hip_stream, lbm_ctx **out);

@@ -47,6 +47,8 @@ int check_params(const lbm_params *p) {
     const int tpw = p->tiles_per_wg;
     if (!(tpw == 0 || tpw == 1 || tpw == 2 || tpw == 4 || tpw == 8))
         return fail(LBM_E_INVAL, "tiles_per_wg must be 0, 1, 2, 4 or 8 (got %d)", tpw);
+    if (p->f16_rounding != 0 && p->f16_rounding != 1)
+        return fail(LBM_E_INVAL, "f16_rounding must be 0 (stochastic) or 1 (nearest) (got %d)", p->f16_rounding);
     return LBM_OK;
 }
 
@@ -167,6 +169,8 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
     P.scale = params->storage == LBM_F16S ? std::ldexp(1.0f, params->f16_log2_scale) : 1.0f;
     P.inv_scale = 1.0f / P.scale;
     P.inv_nfluid = c->n_fluid > 0 ? 1.0 / (double)c->n_fluid : 0.0;
+    P.f16_stochastic = params->storage == LBM_F16S && params->f16_rounding == 0;
+    P.launch_counter = 0;
     *out = c;
     return LBM_OK;
 }
@@ -222,6 +226,7 @@ extern "C" int lbm_step(lbm_ctx *c, int32_t n) {
         void *dst = c->cur ? c->a : c->b;
         hipError_t e = launch_step(c->L, c->P, src, dst);
         if (e != hipSuccess) return hip_fail(e, "lbm_step");
+        c->P.launch_counter++;
         c->cur ^= 1;
     }
     return LBM_OK;
@@ -231,7 +236,9 @@ extern "C" int lbm_step_buf(lbm_ctx *c, const void *src, void *dst) {
     CHECK_CTX(c);
     if (c->n_tiles > 0 && (!src || !dst)) return fail(LBM_E_INVAL, "lbm_step_buf: NULL lattice");
     if (src == dst && c->n_tiles > 0) return fail(LBM_E_INVAL, "lbm_step_buf: src and dst must differ");
-    return launched(launch_step(c->L, c->P, src, dst), "lbm_step_buf");
+    const int rc = launched(launch_step(c->L, c->P, src, dst), "lbm_step_buf");
+    c->P.launch_counter++;
+    return rc;
 }
 
 extern "C" int lbm_current_state(lbm_ctx *c, void **state) {

@@ -61,7 +61,28 @@ template <> struct Codec<LBM_F16S> {
     static constexpr bool PACKED = false;
     static __device__ __forceinline__ T dec(S v, float inv_scale) { return (float)v * inv_scale; }
     static __device__ __forceinline__ S enc(T v, float scale) { return (_Float16)(v * scale); }
+    // Stochastic rounding to FP16: add 13 random bits below the FP16 mantissa
+    // to the FP32 magnitude, then drop them (the conversion is then exact for
+    // normal FP16 values).  Rounds up with probability equal to the dropped
+    // fraction, so the rounding error has zero mean: a per-step increment
+    // smaller than half an ulp is kept on average instead of being lost.
+    static __device__ __forceinline__ S enc_sr(T v, float scale, uint32_t r) {
+        const uint32_t b = (__float_as_uint(v * scale) + (r & 0x1FFFu)) & ~0x1FFFu;
+        return (_Float16)__uint_as_float(b);
+    }
 };
+
+// Counter-based random bits for the FP16 stochastic rounding: one integer
+// hash per node and launch (the "lowbias32" mixer of C. Wellons), then a Weyl
+// sequence over the 19 directions, whose top 13 bits are used.
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
 
 // ---------------------------------------------------------------------------
 // wave -> tile mapping
@@ -369,6 +390,15 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
     int where;
     if (store_slot<S, PK>(own, fl, lane, slot, where)) {
         S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + where;
+        if constexpr (ST == LBM_F16S) {
+            if (a.P.f16_stochastic) {
+                const uint32_t seed = hash32(((uint32_t)t * 64u + (uint32_t)lane) ^ hash32(a.P.launch_counter));
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    store_stream(out + i * TILE, fl ? C::enc_sr(d[i], a.P.scale, (seed + (uint32_t)i * 0x9E3779B9u) >> 19) : S(0));
+                return;
+            }
+        }
 #pragma unroll
         for (int i = 0; i < Q; ++i) store_stream(out + i * TILE, fl ? C::enc(d[i], a.P.scale) : S(0));
     }

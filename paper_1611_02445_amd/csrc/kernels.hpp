@@ -20,6 +20,8 @@ struct Phys {
     float scale;       // FP16: 2^k; 1 otherwise
     float inv_scale;
     double inv_nfluid; // 1 / N_fluid (adjoint loss normalisation)
+    int f16_stochastic;       // FP16 stores with stochastic rounding
+    uint32_t launch_counter;  // step launches so far (seeds the rounding bits)
 };
 
 struct Launch {

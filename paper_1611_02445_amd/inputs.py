@@ -130,17 +130,20 @@ def _capsule_stamp(fluid, p0, p1, r):
     sub |= dist2 <= r * r
 
 
-def vessel_tree(n=512, root_radius=24.0, ratio=0.8, levels=8, length0=None, seed=3, fluid_target=0.05):
+def vessel_tree(n=512, root_radius=24.0, ratio=0.8, levels=8, fluid_target=0.05, seed=3, length0=None):
     """A seeded binary branching network of tubes, mirrored into a loop.
 
-    Half tree: a root tube starts at (0, n/2, n/2) along +x; each segment of
-    level k has radius R0 * ratio^k and length L0 * ratio^k and splits into two
-    children turned by +-theta (theta uniform in 20..45 degrees) in a random
-    plane through the parent axis.  The leaves are extended along +x to the
-    mid-plane x = n/2 - 1/2 and the whole half is mirrored (x -> n-1-x), so the
-    network is a closed loop through the periodic x boundary.  L0 is chosen so
-    that the fluid fraction is close to ``fluid_target`` (a few trials of a
-    simple secant on a coarse estimate).  Returns the bitmap (1 = solid)."""
+    Half tree (x < n/2): a root tube of radius R0 starts at (0, n/2, n/2)
+    heading +x; a segment of level k has radius R0 ratio^k and length
+    L0 ratio^k and ends in two children turned by +-theta (theta uniform in
+    20..45 degrees) in a random plane through the parent axis.  A segment that
+    would leave the half box is reflected back in (its end point is mirrored
+    at the wall it crosses and its direction flipped there).  The leaves are
+    extended along +x to the mid-plane x = n/2 - 1/2 and the half is mirrored
+    (x -> n-1-x), so the network closes into loops through the periodic x
+    boundary.  L0 is bisected so that the fluid fraction is close to
+    ``fluid_target`` (unless ``length0`` is given).  Returns the bitmap
+    (1 = solid) and the L0 used."""
     half = n // 2
 
     def build(L0):
@@ -152,32 +155,47 @@ def vessel_tree(n=512, root_radius=24.0, ratio=0.8, levels=8, length0=None, seed
             r = root_radius * ratio ** k
             L = L0 * ratio ** k
             q = p + L * d
-            q[0] = min(q[0], half - 0.5)
-            q[1:] = np.clip(q[1:], r + 1, n - r - 2)
+            d = d.copy()
+            lo = np.array([0.0, r + 1.0, r + 1.0])
+            hi = np.array([half - 0.5, n - r - 2.0, n - r - 2.0])
+            for a in range(3):
+                if q[a] > hi[a]:
+                    q[a] = max(lo[a], 2 * hi[a] - q[a])
+                    d[a] = -abs(d[a])
+                elif q[a] < lo[a]:
+                    q[a] = min(hi[a], 2 * lo[a] - q[a])
+                    d[a] = abs(d[a])
             _capsule_stamp(fluid, p, q, r)
             if k + 1 < levels:
-                # a random unit vector perpendicular to d defines the plane
                 v = rng.normal(size=3)
                 v -= (v @ d) * d
                 v /= np.linalg.norm(v)
                 for sgn in (1.0, -1.0):
                     th = math.radians(rng.uniform(20.0, 45.0))
                     nd = math.cos(th) * d + sgn * math.sin(th) * v
-                    if nd[0] < 0.2:  # keep the tree heading towards the mirror plane
-                        nd[0] = 0.2
                     nd /= np.linalg.norm(nd)
                     stack.append((q, nd, k + 1))
             else:
-                tail = np.array([half - 0.5, q[1], q[2]])
-                _capsule_stamp(fluid, q, tail, r)
-        full = np.concatenate([fluid, fluid[:, :, ::-1]], axis=2)
-        return full
+                _capsule_stamp(fluid, q, np.array([half - 0.5, q[1], q[2]]), r)
+        return np.concatenate([fluid, fluid[:, :, ::-1]], axis=2)
 
-    if length0 is None:
-        length0 = 0.45 * n
-    geo = build(length0)
-    solid = (~geo).astype(np.uint8)
-    return solid
+    if length0 is not None:
+        geo = build(length0)
+        return (~geo).astype(np.uint8), float(length0)
+    lo_L, hi_L = 0.05 * n, 2.0 * n
+    geo, L0 = None, None
+    for _ in range(14):
+        mid = 0.5 * (lo_L + hi_L)
+        g = build(mid)
+        frac = g.mean()
+        geo, L0 = g, mid
+        if abs(frac - fluid_target) <= 0.002 * fluid_target * 10:
+            break
+        if frac < fluid_target:
+            lo_L = mid
+        else:
+            hi_L = mid
+    return (~geo).astype(np.uint8), float(L0)
 
 
 def perturbation(shape, seed, amplitude=1.0):

@@ -31,13 +31,14 @@ def test_library_exports_every_declared_symbol():
 
 
 def _params(**kw):
-    p = dict(tau=0.8, rho0=1.0, storage=0, model=0, f16_log2_scale=20, tiles_per_wg=0)
+    p = dict(tau=0.8, rho0=1.0, storage=0, model=0, f16_log2_scale=20, tiles_per_wg=0, f16_rounding=0)
     p.update(kw)
     return _abi.Params(**p)
 
 
 @pytest.mark.parametrize("bad", [dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(rho0=0.0),
-                                 dict(storage=3), dict(model=2), dict(f16_log2_scale=31), dict(tiles_per_wg=3)])
+                                 dict(storage=3), dict(model=2), dict(f16_log2_scale=31), dict(tiles_per_wg=3),
+                                 dict(f16_rounding=2)])
 def test_parameter_validation(bad):
     t = Tiling(np.zeros((8, 8, 8), np.uint8), 7)
     sz = _abi.Sizes()
