@@ -15,7 +15,6 @@ workload, permeability after the run, and the FP32 / FP16-shifted storage
 variants with their errors against the FP64 result.
 """
 import argparse
-import hashlib
 import json
 import os
 import re
@@ -37,15 +36,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for name in ("kernels.hip", "common.hpp", "kernels.hpp"):
-        with open(os.path.join(HERE, "paper_1611_02445_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def counter_traffic(kernel_tag, n_launch_units):
+def counter_traffic(kernel_tag):
     """HBM bytes per launch from the committed rocprofv3 counter summary of this
     kernel (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or
     None when there is none or the kernel source changed since it was taken."""
@@ -54,6 +45,7 @@ def counter_traffic(kernel_tag, n_launch_units):
         return None
     with open(path) as fh:
         d = json.load(fh)
+    from paper_1611_02445_amd.profiling import kernel_source_hash
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
     return d.get("hbm_bytes_per_launch")
@@ -202,7 +194,7 @@ def main():
     launch_s = ms_per_step / 1e3
     alg_bytes = BYTES_PER_UPDATE["f64"] * nf
     achieved = alg_bytes / launch_s / 1e9
-    traffic = counter_traffic("step_f64_spheres256", nf)
+    traffic = counter_traffic("step_f64_spheres256")
     log(f"[bench] f64: {mflups:.1f} MFLUPS, {ms_per_step * 1e3:.1f} us/step, {achieved:.0f} GB/s algorithmic")
 
     result = {
@@ -258,7 +250,9 @@ def main():
         u64, uv = r["u"], rv["u"]
         du = torch.linalg.vector_norm(uv - u64).item() / torch.linalg.vector_norm(u64).item()
         dk = abs(rv["k"] - r["k"]) / abs(r["k"])
+        tr = counter_traffic(f"step_{st}_spheres256")
         variants[st] = {"MFLUPS": round(mf, 2), "ms_per_step": round(ms, 6),
+                        "traffic_GBs": None if tr is None else round(tr / (ms / 1e3) / 1e9, 1),
                         "gain_over_f64": round(mf / mflups, 3),
                         "hbm_frac": round(BYTES_PER_UPDATE[st] * nf / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                         "bytes_per_fluid_update": BYTES_PER_UPDATE[st],

@@ -1,0 +1,111 @@
+"""Summaries of rocprofv3 output for the committed performance record.
+
+    python -m paper_1611_02445_amd.profiling trace   <trace_dir> <out.txt> <command...>
+    python -m paper_1611_02445_amd.profiling counters <fetch_dir> <write_dir> <copy_fetch_dir> \
+        <copy_write_dir> <copy_bytes> <kernel_substring> <out.json> <command...>
+
+``trace`` turns a ``rocprofv3 --kernel-trace --stats -f csv`` directory into a
+per-kernel table (calls, average / min / max duration).  ``counters`` turns
+two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of the workload plus the
+same two counters read on a plain device copy of known size (copy_bytes read
+and copy_bytes written) into HBM bytes per launch: each counter is scaled by
+copy_bytes / (the bytes that counter reported for the copy), which calibrates
+what the counter actually counts on this GPU.
+"""
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def kernel_source_hash():
+    """Hash of the kernel sources; a counter summary is valid only for it."""
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "common.hpp", "kernels.hpp"):
+        with open(os.path.join(HERE, "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _find(d, pattern):
+    hits = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no {pattern} under {d}")
+    return hits[0]
+
+
+def trace_table(trace_dir):
+    """{kernel name: (calls, avg_us, min_us, max_us)} from the kernel trace."""
+    path = _find(trace_dir, "*kernel_trace.csv")
+    d = defaultdict(list)
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            d[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    return {k: (len(v), sum(v) / len(v), min(v), max(v)) for k, v in d.items()}
+
+
+def trace_summary(trace_dir, command):
+    rows = sorted(trace_table(trace_dir).items(), key=lambda kv: -kv[1][0] * kv[1][1])
+    out = [f"# rocprofv3 kernel trace: {command}", "",
+           f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10}  kernel"]
+    for name, (n, avg, lo, hi) in rows:
+        out.append(f"{n:6d} {avg:10.2f} {lo:10.2f} {hi:10.2f}  {name}")
+    return "\n".join(out) + "\n"
+
+
+def counter_per_dispatch(pmc_dir, counter, kernel_substring):
+    path = _find(pmc_dir, "*counter_collection.csv")
+    vals = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == counter and kernel_substring in r["Kernel_Name"]:
+                vals.append(float(r["Counter_Value"]))
+    if not vals:
+        raise ValueError(f"no {counter} rows for kernels matching {kernel_substring!r} in {path}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def counters_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, kernel_substring, command):
+    fetch_kib, nf = counter_per_dispatch(fetch_dir, "FETCH_SIZE", kernel_substring)
+    write_kib, nw = counter_per_dispatch(write_dir, "WRITE_SIZE", kernel_substring)
+    cfetch_kib, _ = counter_per_dispatch(cfetch_dir, "FETCH_SIZE", "copyBuffer")
+    cwrite_kib, _ = counter_per_dispatch(cwrite_dir, "WRITE_SIZE", "copyBuffer")
+    fs = copy_bytes / (cfetch_kib * 1024.0)
+    ws = copy_bytes / (cwrite_kib * 1024.0)
+    hbm = fetch_kib * 1024.0 * fs + write_kib * 1024.0 * ws
+    return {
+        "kernel": kernel_substring,
+        "kernel_source_hash": kernel_source_hash(),
+        "command": command,
+        "fetch_size_kib_per_dispatch": fetch_kib,
+        "write_size_kib_per_dispatch": write_kib,
+        "dispatches": [nf, nw],
+        "copy_calibration": {"bytes_read_and_bytes_written_each": copy_bytes, "fetch_size_kib": cfetch_kib,
+                             "write_size_kib": cwrite_kib, "fetch_scale": fs, "write_scale": ws},
+        "hbm_read_bytes_per_launch": fetch_kib * 1024.0 * fs,
+        "hbm_write_bytes_per_launch": write_kib * 1024.0 * ws,
+        "hbm_bytes_per_launch": hbm,
+    }
+
+
+def main(argv):
+    if len(argv) >= 4 and argv[1] == "trace":
+        with open(argv[3], "w") as fh:
+            fh.write(trace_summary(argv[2], " ".join(argv[4:])))
+        return 0
+    if len(argv) >= 10 and argv[1] == "counters":
+        d = counters_summary(argv[2], argv[3], argv[4], argv[5], float(argv[6]), argv[7], " ".join(argv[9:]))
+        with open(argv[8], "w") as fh:
+            json.dump(d, fh, indent=1)
+        return 0
+    print(__doc__, file=sys.stderr)
+    return 2
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv))
