@@ -61,7 +61,7 @@ def build_case(args):
 
 def time_storage(solid, storage, args, torch, want_state=False):
     from paper_1611_02445_amd.lattice import Lattice
-    lat = Lattice(solid, args.tau, periodic=7, storage=storage, tiles_per_wg=args.tpw)
+    lat = Lattice(solid, args.tau, periodic=7, storage=storage, tiles_per_wg=args.tpw, tile_order=args.order)
     lat.init()
     lat.set_force((args.g, 0.0, 0.0))
     log(f"[bench] {storage}: tiles={lat.n_tiles} fluid={lat.n_fluid} eta_t={lat.tiling.eta_t:.4f}")
@@ -99,7 +99,7 @@ def time_calib(solid, args, torch):
     """The paper's measurement kernels on the same tiles and launch shape."""
     from paper_1611_02445_amd.lattice import Lattice
     kind = 1 if args.kernel == "rw" else 2
-    lat = Lattice(solid, args.tau, periodic=7, storage="f64", tiles_per_wg=args.tpw)
+    lat = Lattice(solid, args.tau, periodic=7, storage="f64", tiles_per_wg=args.tpw, tile_order=args.order)
     lat.init()
     a, b = lat.state_a, lat.state_b
     for _ in range(args.warmup):
@@ -155,6 +155,7 @@ def main():
     ap.add_argument("--tau", type=float, default=0.7)
     ap.add_argument("--g", type=float, default=1e-6)
     ap.add_argument("--tpw", type=int, default=0, help="tiles per workgroup (0 = library default)")
+    ap.add_argument("--order", type=int, default=0, help="device tile order (0 = library default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="f32,f16s", help="extra storage variants ('' for none)")

@@ -103,6 +103,10 @@ typedef struct lbm_params {
                                Stochastic rounding draws its bits from a counter-based hash of
                                (tile, node, direction, launch counter): results are reproducible
                                for the same sequence of launches on the context. */
+    int32_t tile_order;     /* order in which the device stores and processes the kept tiles:
+                               0 = library default, 1 = discovery order, 2 / 3 = slabs of 4 / 8
+                               tile planes with z innermost, 4 = Morton.  Only the device layout
+                               changes; every dense input and output is the same for all orders. */
 } lbm_params;
 
 typedef struct lbm_sizes {

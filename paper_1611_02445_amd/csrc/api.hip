@@ -2,6 +2,7 @@
 // lattice ping-pong and kernel launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdlib>
@@ -32,8 +33,15 @@ struct lbm_ctx {
 
 namespace {
 
-size_t storage_size(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
 size_t arith_size(int storage) { return storage == LBM_F64 ? 8 : 4; }
+
+// elements of one lattice of the given storage
+uint64_t lattice_elems(const lbm_tiles *t, int storage) {
+    if (!runs_layout(storage)) return (uint64_t)t->n_tiles * Q * TILE;
+    uint64_t e = 0;
+    for (int64_t i = 0; i < t->n_tiles; ++i) e += run_elems(t->fluid_mask[i], storage);
+    return e;
+}
 
 int check_params(const lbm_params *p) {
     if (!p) return fail(LBM_E_INVAL, "NULL params");
@@ -47,6 +55,8 @@ int check_params(const lbm_params *p) {
     const int tpw = p->tiles_per_wg;
     if (!(tpw == 0 || tpw == 1 || tpw == 2 || tpw == 4 || tpw == 8))
         return fail(LBM_E_INVAL, "tiles_per_wg must be 0, 1, 2, 4 or 8 (got %d)", tpw);
+    if (p->tile_order < 0 || p->tile_order > 4)
+        return fail(LBM_E_INVAL, "tile_order must be in 0..4 (got %d)", p->tile_order);
     if (p->f16_rounding != 0 && p->f16_rounding != 1)
         return fail(LBM_E_INVAL, "f16_rounding must be 0 (stochastic) or 1 (nearest) (got %d)", p->f16_rounding);
     return LBM_OK;
@@ -66,6 +76,43 @@ int hip_fail(hipError_t e, const char *what) {
 
 int default_tpw(int storage) { return storage == LBM_F64 ? 4 : 4; }
 
+// spread the bits of a 21-bit integer three apart (Morton interleave)
+uint64_t spread3(uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+}
+
+// Order in which the device stores and processes the kept tiles (a
+// permutation of the discovery order).  Consecutive device tiles run at the
+// same time on one XCD, so an order that keeps the six face neighbours close
+// lets the partially shared neighbour lines be found in that XCD's L2.
+//   1 discovery (z outer, y, x inner), 2/3 slabs of 4/8 tile planes with z
+//   innermost inside a slab, 4 Morton (bit-interleaved tile coordinates)
+void processing_order(const lbm_tiles *t, int order, std::vector<int32_t> &perm) {
+    const int64_t n = t->n_tiles;
+    perm.resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+    if (order == 1) return;
+    std::vector<uint64_t> key((size_t)n);
+    const uint64_t TX = (uint64_t)t->tx, TY = (uint64_t)t->ty;
+    for (int64_t i = 0; i < n; ++i) {
+        const uint64_t x = (uint64_t)(t->tile_xyz[3 * i] / 4), y = (uint64_t)(t->tile_xyz[3 * i + 1] / 4),
+                       z = (uint64_t)(t->tile_xyz[3 * i + 2] / 4);
+        if (order == 2 || order == 3) {
+            const uint64_t S = order == 2 ? 4 : 8;
+            key[i] = (((z / S) * TY + y) * TX + x) * S + (z % S);
+        } else {
+            key[i] = spread3(x) | spread3(y) << 1 | spread3(z) << 2;
+        }
+    }
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+}
+
 }  // namespace
 
 extern "C" int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *params, lbm_sizes *out) {
@@ -74,11 +121,11 @@ extern "C" int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *para
     if ((rc = check_tiles(tiles)) || (rc = check_params(params))) return rc;
     if (!out) return fail(LBM_E_INVAL, "NULL output");
     const size_t n = (size_t)tiles->n_tiles;
-    out->state_bytes = n * Q * TILE * storage_size(params->storage);
+    out->state_bytes = lattice_elems(tiles, params->storage) * storage_size(params->storage);
     out->table_bytes = TableLayout((int64_t)n).total;
     out->scratch_bytes = (n + 1) * NSUM * sizeof(double);
     out->force_bytes = n * 3 * TILE * arith_size(params->storage);
-    out->adjoint_bytes = n * Q * TILE * arith_size(params->storage);
+    out->adjoint_bytes = lattice_elems(tiles, LBM_F64) * 8;  // FP64 runs, as the FP64 lattice
     out->grad_force_bytes = n * 3 * TILE * sizeof(double);
     out->dense_nodes = (size_t)tiles->nx * (size_t)tiles->ny * (size_t)tiles->nz;
     return LBM_OK;
@@ -113,6 +160,7 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
     if (!c) return fail(LBM_E_NOMEM, "lbm_create: out of host memory");
     c->params = *params;
     if (c->params.tiles_per_wg == 0) c->params.tiles_per_wg = default_tpw(params->storage);
+    if (c->params.tile_order == 0) c->params.tile_order = 1;
     c->nx = tiles->nx;
     c->ny = tiles->ny;
     c->nz = tiles->nz;
@@ -125,19 +173,37 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
     c->tables = tables;
     c->scratch = reinterpret_cast<double *>(scratch);
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    c->state_bytes = (size_t)n * Q * TILE * storage_size(params->storage);
+    c->state_bytes = lattice_elems(tiles, params->storage) * storage_size(params->storage);
     if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
 
     const TableLayout lay(n);
     if (n > 0) {
+        // device tile d holds discovery tile perm[d]; neighbour numbers are
+        // translated with the inverse permutation
+        std::vector<int32_t> perm, inv;
+        processing_order(tiles, c->params.tile_order, perm);
+        inv.assign((size_t)n, 0);
+        for (int64_t d = 0; d < n; ++d) inv[perm[d]] = (int32_t)d;
         std::vector<unsigned char> host(lay.total, 0);
-        memcpy(host.data() + lay.mask_off, tiles->fluid_mask, (size_t)n * 8);
+        TileRec *rec = reinterpret_cast<TileRec *>(host.data() + lay.rec_off);
         int32_t *nb = reinterpret_cast<int32_t *>(host.data() + lay.nbr_off);
         int32_t *xyz = reinterpret_cast<int32_t *>(host.data() + lay.xyz_off);
-        for (int64_t i = 0; i < n; ++i) {
-            for (int k = 0; k < NBR_STRIDE; ++k) nb[NBR_STRIDE * i + k] = k < 27 ? tiles->nbr[27 * i + k] : -1;
-            for (int a = 0; a < 3; ++a) xyz[4 * i + a] = tiles->tile_xyz[3 * i + a];
-            xyz[4 * i + 3] = 0;
+        uint64_t next = 0;
+        for (int64_t d = 0; d < n; ++d) {
+            const int64_t i = perm[d];
+            rec[d].mask = tiles->fluid_mask[i];
+            if (runs_layout(params->storage)) {
+                rec[d].base = next;
+                next += run_elems(tiles->fluid_mask[i], params->storage);
+            } else {
+                rec[d].base = (uint64_t)d * Q * TILE;
+            }
+            for (int k = 0; k < NBR_STRIDE; ++k) {
+                const int32_t v = k < 27 ? tiles->nbr[27 * i + k] : -1;
+                nb[NBR_STRIDE * d + k] = v < 0 ? -1 : inv[v];
+            }
+            for (int a = 0; a < 3; ++a) xyz[4 * d + a] = tiles->tile_xyz[3 * i + a];
+            xyz[4 * d + 3] = 0;
         }
         hipError_t e = hipMemcpyAsync(tables, host.data(), lay.total, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -151,11 +217,12 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
     c->L.n_tiles = (int)n;
     c->L.tpw = c->params.tiles_per_wg;
     c->L.grid = (int)((n + c->L.tpw - 1) / c->L.tpw);
-    c->L.tb.mask = reinterpret_cast<const uint64_t *>(tb + lay.mask_off);
+    c->L.tb.rec = reinterpret_cast<const TileRec *>(tb + lay.rec_off);
     c->L.tb.nbr = reinterpret_cast<const int32_t *>(tb + lay.nbr_off);
     c->L.tb.xyz = reinterpret_cast<const int32_t *>(tb + lay.xyz_off);
-    // lattice byte offsets (adjoint lattices are FP64, 8 B) must fit 32 bits
-    c->L.off32 = (size_t)n * Q * TILE * 8 <= (size_t)UINT32_MAX;
+    // every byte offset into a lattice (an FP64 adjoint lattice has the same
+    // elements as the FP64 lattice) must fit 32 bits for the 32-bit kernels
+    c->L.off32 = c->state_bytes <= (size_t)UINT32_MAX;
 
     Phys &P = c->P;
     P = Phys{};

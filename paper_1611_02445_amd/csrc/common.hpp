@@ -36,25 +36,46 @@ constexpr double weight(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.
 constexpr int TILE = 64;
 
 // ---------------------------------------------------------------------------
+// lattice layout
+//   runs  (FP64, FP32): tile t with k fluid nodes owns one contiguous run of
+//         19*k values, direction i at base[t] + i*k + slot, slot = number of
+//         fluid nodes of the tile below the node; the run is padded to whole
+//         128-byte lines
+//   plain (FP16): tile t owns 19 blocks of 64 values at t*19*64 + i*64 + n;
+//         a block is exactly one 128-byte line
+// ---------------------------------------------------------------------------
+inline size_t storage_size(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
+inline bool runs_layout(int storage) { return storage != LBM_F16S; }
+inline uint64_t run_elems(uint64_t mask, int storage) {
+    const uint64_t L = 128 / storage_size(storage);
+    const uint64_t k = (uint64_t)__builtin_popcountll(mask);
+    return (Q * k + L - 1) / L * L;
+}
+
+// ---------------------------------------------------------------------------
 // device table layout inside the caller's `tables` buffer
-//   [0]            uint64 fluid mask per tile
+//   [rec_off]      TileRec per tile: fluid mask, element offset of its data
 //   [nbr_off]      int32 [n_tiles][32]: the 27 neighbours, padded with -1
 //   [xyz_off]      int32 [n_tiles][4]:  corner x, y, z, 0
 // ---------------------------------------------------------------------------
+struct TileRec {
+    uint64_t mask;
+    uint64_t base;
+};
 constexpr int NBR_STRIDE = 32;
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct TableLayout {
-    size_t mask_off, nbr_off, xyz_off, total;
+    size_t rec_off, nbr_off, xyz_off, total;
     explicit TableLayout(int64_t n_tiles) {
-        mask_off = 0;
-        nbr_off = align_up(mask_off + (size_t)n_tiles * 8, 256);
+        rec_off = 0;
+        nbr_off = align_up(rec_off + (size_t)n_tiles * sizeof(TileRec), 256);
         xyz_off = align_up(nbr_off + (size_t)n_tiles * NBR_STRIDE * 4, 256);
         total = align_up(xyz_off + (size_t)n_tiles * 16, 256);
     }
 };
 
 struct DevTables {
-    const uint64_t *mask;
+    const TileRec *rec;
     const int32_t *nbr;
     const int32_t *xyz;
 };

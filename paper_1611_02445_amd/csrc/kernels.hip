@@ -44,21 +44,21 @@ template <int ST> struct Codec;
 template <> struct Codec<LBM_F64> {
     using S = double;
     using T = double;
-    static constexpr bool PACKED = true;
+    static constexpr bool RUNS = true;
     static __device__ __forceinline__ T dec(S v, float) { return v; }
     static __device__ __forceinline__ S enc(T v, float) { return v; }
 };
 template <> struct Codec<LBM_F32> {
     using S = float;
     using T = float;
-    static constexpr bool PACKED = true;
+    static constexpr bool RUNS = true;
     static __device__ __forceinline__ T dec(S v, float) { return v; }
     static __device__ __forceinline__ S enc(T v, float) { return v; }
 };
 template <> struct Codec<LBM_F16S> {
     using S = _Float16;
     using T = float;
-    static constexpr bool PACKED = false;
+    static constexpr bool RUNS = false;
     static __device__ __forceinline__ T dec(S v, float inv_scale) { return (float)v * inv_scale; }
     static __device__ __forceinline__ S enc(T v, float scale) { return (_Float16)(v * scale); }
     // Stochastic rounding to FP16: add 13 random bits below the FP16 mantissa
@@ -72,9 +72,10 @@ template <> struct Codec<LBM_F16S> {
     }
 };
 
-// Counter-based random bits for the FP16 stochastic rounding: one integer
-// hash per node and launch (the "lowbias32" mixer of C. Wellons), then a Weyl
-// sequence over the 19 directions, whose top 13 bits are used.
+// Counter-based random bits for the FP16 stochastic rounding: an integer hash
+// (the "lowbias32" mixer of C. Wellons) of the node's coordinates and the
+// launch counter, then a Weyl sequence over the 19 directions, whose top 13
+// bits are used.
 __device__ __forceinline__ uint32_t hash32(uint32_t x) {
     x ^= x >> 16;
     x *= 0x7feb352du;
@@ -110,32 +111,47 @@ __device__ __forceinline__ int mbcnt(uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// slot of this lane's node in its own tile
-template <bool PACKED>
-__device__ __forceinline__ int own_slot(uint64_t own, int lane) {
-    if constexpr (PACKED) return mbcnt(own);
-    else return lane;
-}
-
 // ---------------------------------------------------------------------------
 // neighbourhood of a tile (wave-uniform: lives in SGPRs)
 // ---------------------------------------------------------------------------
+template <typename OffT>
 struct Nbhd {
-    int nb[27];
-    uint64_t m[27];
+    uint64_t m[27];  // fluid masks (0 for a missing neighbour)
+    OffT base[27];   // element offset of each neighbour's data
 };
 
-__device__ __forceinline__ void load_nbhd(Nbhd &h, const DevTables &tb, int t) {
+template <typename OffT>
+__device__ __forceinline__ void load_nbhd(Nbhd<OffT> &h, const DevTables &tb, int t) {
     const int32_t *row = tb.nbr + (size_t)t * NBR_STRIDE;
 #pragma unroll
-    for (int k = 0; k < 27; ++k) h.nb[k] = row[k];
-#pragma unroll
     for (int k = 0; k < 27; ++k) {
-        const int j = h.nb[k];
-        const uint64_t mk = tb.mask[j < 0 ? 0 : j];
-        h.m[k] = j < 0 ? 0ull : mk;
+        const int j = row[k];
+        const TileRec r = tb.rec[j < 0 ? 0 : j];
+        h.m[k] = j < 0 ? 0ull : r.mask;
+        h.base[k] = (OffT)r.base;
     }
 }
+
+// where this lane's own values live
+template <bool RUNS, typename OffT>
+struct Self {
+    OffT base;    // element offset of the tile's data
+    OffT stride;  // elements between directions: k (runs) or 64 (plain)
+    int slot;     // this node's slot in each block
+    int k;        // fluid nodes of the tile
+    __device__ __forceinline__ Self(const TileRec &r, int lane) {
+        base = (OffT)r.base;
+        k = __builtin_popcountll(r.mask);
+        if constexpr (RUNS) {
+            stride = (OffT)k;
+            slot = mbcnt(r.mask);
+        } else {
+            stride = (OffT)TILE;
+            slot = lane;
+        }
+    }
+    __device__ __forceinline__ OffT elem(int i) const { return base + (OffT)i * stride + (OffT)slot; }
+};
 
 // lanes whose source node (x+sx, y+sy, z+sz) leaves the tile exactly along the
 // axes flagged bx, by, bz
@@ -161,8 +177,8 @@ struct Region {
 };
 
 // bits of the neighbour mask that one region's lanes read, aligned to lanes
-template <class R>
-__device__ __forceinline__ uint64_t region_source_bits(const Nbhd &h) {
+template <class R, class H>
+__device__ __forceinline__ uint64_t region_source_bits(const H &h) {
     if constexpr (!R::EXISTS) {
         return 0ull;
     } else {
@@ -171,16 +187,16 @@ __device__ __forceinline__ uint64_t region_source_bits(const Nbhd &h) {
     }
 }
 
-template <int SX, int SY, int SZ, int BX, int BY, int BZ>
-__device__ __forceinline__ uint64_t region_fluid(const Nbhd &h) {
+template <int SX, int SY, int SZ, int BX, int BY, int BZ, class H>
+__device__ __forceinline__ uint64_t region_fluid(const H &h) {
     using R = Region<SX, SY, SZ, BX, BY, BZ>;
     if constexpr (!R::EXISTS) return 0ull;
     else return region_source_bits<R>(h) & R::LANES;
 }
 
 // 64-bit mask: bit n set when lane n's source node exists and is fluid
-template <int SX, int SY, int SZ>
-__device__ __forceinline__ uint64_t source_fluid(const Nbhd &h) {
+template <int SX, int SY, int SZ, class H>
+__device__ __forceinline__ uint64_t source_fluid(const H &h) {
     return region_fluid<SX, SY, SZ, 0, 0, 0>(h) | region_fluid<SX, SY, SZ, 1, 0, 0>(h) |
            region_fluid<SX, SY, SZ, 0, 1, 0>(h) | region_fluid<SX, SY, SZ, 1, 1, 0>(h) |
            region_fluid<SX, SY, SZ, 0, 0, 1>(h) | region_fluid<SX, SY, SZ, 1, 0, 1>(h) |
@@ -188,29 +204,29 @@ __device__ __forceinline__ uint64_t source_fluid(const Nbhd &h) {
 }
 
 // Element index (within the lattice) of direction I's value at this lane's
-// source node, for the lanes of one region:
-//   plain : (tile K) * 19 * 64 + I * 64 + lane + OFF
-//   packed: (tile K) * 19 * 64 + I * 64 + mbcnt(m_K shifted by OFF) + c,
-//           c = popcount(m_K below OFF) when OFF > 0
+// source node, for the lanes of one region (tile K, in-tile node lane + OFF):
+//   plain: base_K + I * 64 + lane + OFF
+//   runs : base_K + I * k_K + mbcnt(m_K shifted by OFF) + c,
+//          k_K = popcount(m_K), c = popcount(m_K below OFF) when OFF > 0
 // Every term but the mbcnt is wave-uniform.
-template <class R, int I, bool PACKED, typename OffT>
-__device__ __forceinline__ OffT region_elem(const Nbhd &h, int lane) {
-    const OffT tile_base = (OffT)h.nb[R::K] * (OffT)(Q * TILE) + (OffT)(I * TILE);
-    if constexpr (PACKED) {
+template <class R, int I, bool RUNS, typename OffT>
+__device__ __forceinline__ OffT region_elem(const Nbhd<OffT> &h, int lane) {
+    const uint64_t mk = h.m[R::K];
+    if constexpr (RUNS) {
         constexpr int POS = R::OFF > 0 ? R::OFF : 0;
-        const uint64_t mk = h.m[R::K];
         const int c = POS ? __builtin_popcountll(mk & ((1ull << POS) - 1ull)) : 0;
-        return (OffT)mbcnt(region_source_bits<R>(h)) + (tile_base + (OffT)c);
+        const OffT blk = (OffT)h.base[R::K] + (OffT)I * (OffT)__builtin_popcountll(mk) + (OffT)c;
+        return (OffT)mbcnt(region_source_bits<R>(h)) + blk;
     } else {
-        return (OffT)lane + (tile_base + (OffT)R::OFF);
+        return (OffT)lane + ((OffT)h.base[R::K] + (OffT)(I * TILE + R::OFF));
     }
 }
 
-template <int SX, int SY, int SZ, int BX, int BY, int BZ, int I, bool PACKED, typename OffT>
-__device__ __forceinline__ OffT region_pick(const Nbhd &h, int lane, OffT cur) {
+template <int SX, int SY, int SZ, int BX, int BY, int BZ, int I, bool RUNS, typename OffT>
+__device__ __forceinline__ OffT region_pick(const Nbhd<OffT> &h, int lane, OffT cur) {
     using R = Region<SX, SY, SZ, BX, BY, BZ>;
     if constexpr (!R::EXISTS) return cur;
-    else return lane_on(R::LANES) ? region_elem<R, I, PACKED, OffT>(h, lane) : cur;
+    else return lane_on(R::LANES) ? region_elem<R, I, RUNS, OffT>(h, lane) : cur;
 }
 
 template <typename OffT, typename S>
@@ -222,58 +238,76 @@ __device__ __forceinline__ S load_elem(const char *base, OffT elem) {
 // node x - c_I (REV = false: pull streaming S) or x + c_I (REV = true: its
 // transpose S^T), or, when that node is solid or missing, the value of the
 // opposite direction at the node itself (halfway bounce-back).
-template <int I, bool REV, bool PACKED, typename S, typename OffT>
-__device__ __forceinline__ S gather_one(const Nbhd &h, const char *base, int t, int lane, int slot) {
-    const OffT self = (OffT)t * (OffT)(Q * TILE) + (OffT)slot;
+template <int I, bool REV, bool RUNS, typename S, typename OffT>
+__device__ __forceinline__ S gather_one(const Nbhd<OffT> &h, const char *base, const Self<RUNS, OffT> &me, int lane) {
     if constexpr (I == 0) {
-        return load_elem<OffT, S>(base, self);
+        return load_elem<OffT, S>(base, me.elem(0));
     } else {
         constexpr int SX = REV ? CX[I] : -CX[I];
         constexpr int SY = REV ? CY[I] : -CY[I];
         constexpr int SZ = REV ? CZ[I] : -CZ[I];
         constexpr int OP = opposite(I);
         const uint64_t ok_mask = source_fluid<SX, SY, SZ>(h);
-        OffT e = region_elem<Region<SX, SY, SZ, 0, 0, 0>, I, PACKED, OffT>(h, lane);
-        e = region_pick<SX, SY, SZ, 1, 0, 0, I, PACKED, OffT>(h, lane, e);
-        e = region_pick<SX, SY, SZ, 0, 1, 0, I, PACKED, OffT>(h, lane, e);
-        e = region_pick<SX, SY, SZ, 1, 1, 0, I, PACKED, OffT>(h, lane, e);
-        e = region_pick<SX, SY, SZ, 0, 0, 1, I, PACKED, OffT>(h, lane, e);
-        e = region_pick<SX, SY, SZ, 1, 0, 1, I, PACKED, OffT>(h, lane, e);
-        e = region_pick<SX, SY, SZ, 0, 1, 1, I, PACKED, OffT>(h, lane, e);
-        e = region_pick<SX, SY, SZ, 1, 1, 1, I, PACKED, OffT>(h, lane, e);
-        const OffT bb = self + (OffT)(OP * TILE);
-        return load_elem<OffT, S>(base, lane_on(ok_mask) ? e : bb);
+        OffT e = region_elem<Region<SX, SY, SZ, 0, 0, 0>, I, RUNS, OffT>(h, lane);
+        e = region_pick<SX, SY, SZ, 1, 0, 0, I, RUNS, OffT>(h, lane, e);
+        e = region_pick<SX, SY, SZ, 0, 1, 0, I, RUNS, OffT>(h, lane, e);
+        e = region_pick<SX, SY, SZ, 1, 1, 0, I, RUNS, OffT>(h, lane, e);
+        e = region_pick<SX, SY, SZ, 0, 0, 1, I, RUNS, OffT>(h, lane, e);
+        e = region_pick<SX, SY, SZ, 1, 0, 1, I, RUNS, OffT>(h, lane, e);
+        e = region_pick<SX, SY, SZ, 0, 1, 1, I, RUNS, OffT>(h, lane, e);
+        e = region_pick<SX, SY, SZ, 1, 1, 1, I, RUNS, OffT>(h, lane, e);
+        return load_elem<OffT, S>(base, lane_on(ok_mask) ? e : me.elem(OP));
     }
 }
 
-template <bool REV, bool PACKED, typename S, typename OffT, int... Is>
-__device__ __forceinline__ void gather_all_impl(S (&v)[Q], const Nbhd &h, const char *base, int t, int lane,
-                                                int slot, std::integer_sequence<int, Is...>) {
-    ((v[Is] = gather_one<Is, REV, PACKED, S, OffT>(h, base, t, lane, slot)), ...);
+template <bool REV, bool RUNS, typename S, typename OffT, int... Is>
+__device__ __forceinline__ void gather_all_impl(S (&v)[Q], const Nbhd<OffT> &h, const char *base,
+                                                const Self<RUNS, OffT> &me, int lane,
+                                                std::integer_sequence<int, Is...>) {
+    ((v[Is] = gather_one<Is, REV, RUNS, S, OffT>(h, base, me, lane)), ...);
 }
 
-template <bool REV, bool PACKED, typename S, typename OffT>
-__device__ __forceinline__ void gather_all(S (&v)[Q], const Nbhd &h, const char *base, int t, int lane, int slot) {
-    gather_all_impl<REV, PACKED, S, OffT>(v, h, base, t, lane, slot, std::make_integer_sequence<int, Q>{});
+template <bool REV, bool RUNS, typename S, typename OffT>
+__device__ __forceinline__ void gather_all(S (&v)[Q], const Nbhd<OffT> &h, const char *base, const Self<RUNS, OffT> &me,
+                                           int lane) {
+    gather_all_impl<REV, RUNS, S, OffT>(v, h, base, me, lane, std::make_integer_sequence<int, Q>{});
 }
 
 // ---------------------------------------------------------------------------
-// where each lane stores
+// writing a tile's values
 // ---------------------------------------------------------------------------
-// Every 128-byte line of a block that holds a fluid value is written whole:
-// lanes of solid nodes store a zero (never read) into the line's other slots,
-// lines without fluid values are neither read nor written.
-//   packed: fluid lane -> its slot; the j-th solid lane -> slot k + j while
-//           that is below k rounded up to a whole line (k = fluid nodes)
-//   plain : every lane of a line holding a fluid node, at slot = lane
-template <typename S, bool PACKED>
-__device__ __forceinline__ bool store_slot(uint64_t own, bool fl, int lane, int slot, int &where) {
+// Every 128-byte line a tile writes is written whole, and lines that hold no
+// fluid value are neither read nor written.
+//   runs : fluid lanes write their 19 values; then lanes 0..pad-1 write zeros
+//          after the run's 19*k values up to the next line boundary
+//   plain: every lane of a line holding a fluid node writes, solid ones a zero
+template <typename S>
+__device__ __forceinline__ void store_stream(S *p, S v) {
+    __builtin_nontemporal_store(v, p);
+}
+
+template <typename S, bool RUNS, typename OffT, bool STREAM, class Value>
+__device__ __forceinline__ void store_tile(char *lattice, const Self<RUNS, OffT> &me, uint64_t own, bool fl, int lane,
+                                           Value value) {
+    S *out = reinterpret_cast<S *>(lattice);
     constexpr int L = 128 / (int)sizeof(S);
-    if constexpr (PACKED) {
-        const int k = __builtin_popcountll(own);
-        const int top = (k + L - 1) / L * L;
-        where = fl ? slot : k + (lane - slot);
-        return where < top;
+    if constexpr (RUNS) {
+        if (fl) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                // wave-uniform block start + this lane's slot
+                S *p = out + (me.base + (OffT)i * me.stride) + me.slot;
+                if constexpr (STREAM) store_stream(p, value(i));
+                else *p = value(i);
+            }
+        }
+        const int used = Q * me.k;
+        const int pad = (used + L - 1) / L * L - used;
+        if (lane < pad) {
+            S *p = out + me.base + (OffT)(used + lane);
+            if constexpr (STREAM) store_stream(p, S(0));
+            else *p = S(0);
+        }
     } else {
         uint64_t cover = 0;
         if constexpr (L >= 64) {
@@ -284,15 +318,16 @@ __device__ __forceinline__ bool store_slot(uint64_t own, bool fl, int lane, int 
             for (int g = 0; g < 64 / L; ++g)
                 if ((own >> (g * L)) & G) cover |= G << (g * L);
         }
-        where = lane;
-        return lane_on(cover);
+        if (lane_on(cover)) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                S *p = out + me.elem(i);
+                const S v = fl ? value(i) : S(0);
+                if constexpr (STREAM) store_stream(p, v);
+                else *p = v;
+            }
+        }
     }
-}
-
-// the output lattice is not read again by this launch: stream it past the caches
-template <typename S>
-__device__ __forceinline__ void store_stream(S *p, S v) {
-    __builtin_nontemporal_store(v, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -368,75 +403,70 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
     using C = Codec<ST>;
     using S = typename C::S;
     using T = typename C::T;
-    constexpr bool PK = C::PACKED;
+    constexpr bool RN = C::RUNS;
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const uint64_t own = a.tb.mask[t];
+    const TileRec rec = a.tb.rec[t];
+    const uint64_t own = rec.mask;
     const bool fl = lane_on(own);
-    const int slot = own_slot<PK>(own, lane);
+    const Self<RN, OffT> me(rec, lane);
     T d[Q];
     if (fl) {  // solid nodes neither gather nor collide
-        Nbhd h;
+        Nbhd<OffT> h;
         load_nbhd(h, a.tb, t);
         S raw[Q];
-        gather_all<false, PK, S, OffT>(raw, h, a.src, t, lane, slot);
+        gather_all<false, RN, S, OffT>(raw, h, a.src, me, lane);
 #pragma unroll
         for (int i = 0; i < Q; ++i) d[i] = C::dec(raw[i], a.P.inv_scale);
         T Fx, Fy, Fz;
         load_force<T>(a.P, t, lane, Fx, Fy, Fz);
         collide<T, MODEL>(d, T(a.P.rho_base), T(a.P.omega), T(a.P.kg), Fx, Fy, Fz);
     }
-    int where;
-    if (store_slot<S, PK>(own, fl, lane, slot, where)) {
-        S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + where;
-        if constexpr (ST == LBM_F16S) {
-            if (a.P.f16_stochastic) {
-                const uint32_t seed = hash32(((uint32_t)t * 64u + (uint32_t)lane) ^ hash32(a.P.launch_counter));
-#pragma unroll
-                for (int i = 0; i < Q; ++i)
-                    store_stream(out + i * TILE, fl ? C::enc_sr(d[i], a.P.scale, (seed + (uint32_t)i * 0x9E3779B9u) >> 19) : S(0));
-                return;
-            }
+    if constexpr (ST == LBM_F16S) {
+        if (a.P.f16_stochastic) {
+            // keyed on the node's position, not on where the tile is stored
+            const int32_t *c = a.tb.xyz + 4 * (size_t)t;
+            const uint32_t tile_seed =
+                hash32((uint32_t)c[0] + hash32((uint32_t)c[1] + hash32((uint32_t)c[2] + hash32(a.P.launch_counter))));
+            const uint32_t seed = hash32(tile_seed + (uint32_t)lane);
+            store_tile<S, RN, OffT, true>(a.dst, me, own, fl, lane, [&](int i) {
+                return C::enc_sr(d[i], a.P.scale, (seed + (uint32_t)i * 0x9E3779B9u) >> 19);
+            });
+            return;
         }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) store_stream(out + i * TILE, fl ? C::enc(d[i], a.P.scale) : S(0));
     }
+    store_tile<S, RN, OffT, true>(a.dst, me, own, fl, lane, [&](int i) { return C::enc(d[i], a.P.scale); });
 }
 
 // the paper's measurement kernels (Section 4.1): kind 1 "read/write only",
 // kind 2 "propagation only"
-template <typename S, bool PK, int KIND, typename OffT>
+template <typename S, bool RN, int KIND, typename OffT>
 __global__ __launch_bounds__(512) void k_calib(KArgs a) {
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const uint64_t own = a.tb.mask[t];
+    const TileRec rec = a.tb.rec[t];
+    const uint64_t own = rec.mask;
     const bool fl = lane_on(own);
-    const int slot = own_slot<PK>(own, lane);
+    const Self<RN, OffT> me(rec, lane);
     S v[Q];
     if (fl) {
         if constexpr (KIND == 1) {
-            const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + slot;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) v[i] = in[i * TILE];
+            for (int i = 0; i < Q; ++i) v[i] = load_elem<OffT, S>(a.src, me.elem(i));
         } else {
-            Nbhd h;
+            Nbhd<OffT> h;
             load_nbhd(h, a.tb, t);
-            gather_all<false, PK, S, OffT>(v, h, a.src, t, lane, slot);
+            gather_all<false, RN, S, OffT>(v, h, a.src, me, lane);
         }
     }
-    int where;
-    if (store_slot<S, PK>(own, fl, lane, slot, where)) {
-        S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + where;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) store_stream(out + i * TILE, fl ? v[i] : S(0));
-    }
+    store_tile<S, RN, OffT, true>(a.dst, me, own, fl, lane, [&](int i) { return v[i]; });
 }
 
 // ---------------------------------------------------------------------------
-// initial state: feq(rho0, u0) at every fluid slot of both lattices, 0 in all
-// other slots
+// initial state: feq(rho0, u0) at every fluid node of both lattices, 0 in the
+// padding
 // ---------------------------------------------------------------------------
 template <int ST>
 __global__ __launch_bounds__(512) void k_init(KArgs a, char *b, double ux, double uy, double uz) {
@@ -444,22 +474,29 @@ __global__ __launch_bounds__(512) void k_init(KArgs a, char *b, double ux, doubl
     using S = typename C::S;
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
-    const int lane = (int)(threadIdx.x & 63);  // = slot here
-    const uint64_t own = a.tb.mask[t];
-    const bool used = C::PACKED ? lane < __builtin_popcountll(own) : (bool)((own >> lane) & 1);
+    const int lane = (int)(threadIdx.x & 63);
+    const TileRec rec = a.tb.rec[t];
+    const bool fl = (rec.mask >> lane) & 1;
+    const Self<C::RUNS, uint64_t> me(rec, lane);
     const double rho = a.P.rho0;
     const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
-    S *pa = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + lane;
-    S *pb = reinterpret_cast<S *>(b) + (size_t)t * Q * TILE + lane;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    auto feq = [&](int i) {
         const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
         const double P = 3.0 * cu + 4.5 * cu * cu - usq;
-        const double feq = (a.P.model == LBM_QUASI_COMPRESSIBLE) ? weight(i) * rho * (1.0 + P) : weight(i) * (rho + P);
-        const double dv = feq - weight(i) * a.P.rho_base;
-        const S v = used ? C::enc((typename C::T)dv, a.P.scale) : S(0);
-        pa[i * TILE] = v;
-        pb[i * TILE] = v;
+        const double f = (a.P.model == LBM_QUASI_COMPRESSIBLE) ? weight(i) * rho * (1.0 + P) : weight(i) * (rho + P);
+        return C::enc((typename C::T)(f - weight(i) * a.P.rho_base), a.P.scale);
+    };
+    if constexpr (C::RUNS) {
+        store_tile<S, true, uint64_t, false>(a.dst, me, rec.mask, fl, lane, feq);
+        store_tile<S, true, uint64_t, false>(b, me, rec.mask, fl, lane, feq);
+    } else {  // every slot of the 19 blocks, so solid slots start at 0 too
+        S *pa = reinterpret_cast<S *>(a.dst), *pb = reinterpret_cast<S *>(b);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const S v = fl ? feq(i) : S(0);
+            pa[me.elem(i)] = v;
+            pb[me.elem(i)] = v;
+        }
     }
 }
 
@@ -497,15 +534,14 @@ __global__ __launch_bounds__(512) void k_macro(KArgs a, double *rho_out, double 
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const uint64_t own = a.tb.mask[t];
-    const bool fl = (own >> lane) & 1;
-    const int slot = own_slot<C::PACKED>(own, lane);
+    const TileRec rec = a.tb.rec[t];
+    const bool fl = (rec.mask >> lane) & 1;
+    const Self<C::RUNS, uint64_t> me(rec, lane);
     double drho = 0, jx = 0, jy = 0, jz = 0;
     if (fl) {
-        const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + slot;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const double v = (double)C::dec(in[i * TILE], a.P.inv_scale);
+            const double v = (double)C::dec(load_elem<uint64_t, S>(a.src, me.elem(i)), a.P.inv_scale);
             drho += v;
             jx += CX[i] * v;
             jy += CY[i] * v;
@@ -593,19 +629,17 @@ __global__ __launch_bounds__(512) void k_get_state(KArgs a, double *dense, int n
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const uint64_t own = a.tb.mask[t];
-    if (!((own >> lane) & 1)) return;  // the dense array was zero-filled
-    const int slot = own_slot<C::PACKED>(own, lane);
+    const TileRec rec = a.tb.rec[t];
+    if (!((rec.mask >> lane) & 1)) return;  // the dense array was zero-filled
+    const Self<C::RUNS, uint64_t> me(rec, lane);
     const size_t N = (size_t)nx * ny * nz;
     const size_t n = dense_index(a.tb.xyz + 4 * (size_t)t, lane, nx, ny);
-    const S *in = reinterpret_cast<const S *>(a.src) + (size_t)t * Q * TILE + slot;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        dense[(size_t)i * N + n] = (double)C::dec(in[i * TILE], a.P.inv_scale) + weight(i) * a.P.rho_base;
+        dense[(size_t)i * N + n] =
+            (double)C::dec(load_elem<uint64_t, S>(a.src, me.elem(i)), a.P.inv_scale) + weight(i) * a.P.rho_base;
 }
 
-// every slot is written once: fluid lanes their value at their slot, solid
-// lanes a zero at the slots left over
 template <int ST>
 __global__ __launch_bounds__(512) void k_set_state(KArgs a, const double *dense, int nx, int ny, int nz) {
     using C = Codec<ST>;
@@ -614,17 +648,20 @@ __global__ __launch_bounds__(512) void k_set_state(KArgs a, const double *dense,
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const uint64_t own = a.tb.mask[t];
-    const bool fl = (own >> lane) & 1;
-    const int slot = own_slot<C::PACKED>(own, lane);
-    const int where = fl ? slot : (C::PACKED ? __builtin_popcountll(own) + (lane - slot) : lane);
+    const TileRec rec = a.tb.rec[t];
+    const bool fl = (rec.mask >> lane) & 1;
+    const Self<C::RUNS, uint64_t> me(rec, lane);
     const size_t N = (size_t)nx * ny * nz;
     const size_t n = dense_index(a.tb.xyz + 4 * (size_t)t, lane, nx, ny);
-    S *out = reinterpret_cast<S *>(a.dst) + (size_t)t * Q * TILE + where;
+    auto value = [&](int i) {
+        return C::enc((T)(dense[(size_t)i * N + n] - weight(i) * a.P.rho_base), a.P.scale);
+    };
+    if constexpr (C::RUNS) {
+        store_tile<S, true, uint64_t, false>(a.dst, me, rec.mask, fl, lane, value);
+    } else {
+        S *out = reinterpret_cast<S *>(a.dst);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const double v = fl ? dense[(size_t)i * N + n] - weight(i) * a.P.rho_base : 0.0;
-        out[i * TILE] = fl ? C::enc((T)v, a.P.scale) : S(0);
+        for (int i = 0; i < Q; ++i) out[me.elem(i)] = fl ? value(i) : S(0);
     }
 }
 
@@ -633,7 +670,7 @@ __global__ __launch_bounds__(512) void k_force_to_tiles(KArgs a, const double *g
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const bool fl = (a.tb.mask[t] >> lane) & 1;
+    const bool fl = (a.tb.rec[t].mask >> lane) & 1;
     const size_t N = (size_t)nx * ny * nz;
     const size_t n = dense_index(a.tb.xyz + 4 * (size_t)t, lane, nx, ny);
     T *o = out + (size_t)t * 3 * TILE + lane;
@@ -647,14 +684,14 @@ __global__ __launch_bounds__(512) void k_tiles_to_dense(KArgs a, const T *in, in
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const bool fl = (a.tb.mask[t] >> lane) & 1;
+    const bool fl = (a.tb.rec[t].mask >> lane) & 1;
     const size_t N = (size_t)nx * ny * nz;
     const size_t n = dense_index(a.tb.xyz + 4 * (size_t)t, lane, nx, ny);
     for (int c = 0; c < ncomp; ++c) dense[(size_t)c * N + n] = fl ? (double)in[((size_t)t * ncomp + c) * TILE + lane] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
-// discrete adjoint (quasi-compressible, FP64, packed slots)
+// discrete adjoint (quasi-compressible, FP64, runs layout)
 //
 // For the local collision C(g, F) with rho = sum g, u = (sum c g + F/2)/rho:
 //   (J^T lam)_j = (1 - 1/tau) lam_j + A + V.(c_j - u)/rho
@@ -724,15 +761,6 @@ struct AdjArgs {
     Phys P;
 };
 
-__device__ __forceinline__ void store_adjoint(double *tile_out, uint64_t own, bool fl, int lane, int slot,
-                                              const double (&v)[Q]) {
-    int where;
-    if (store_slot<double, true>(own, fl, lane, slot, where)) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) tile_out[i * TILE + where] = fl ? v[i] : 0.0;
-    }
-}
-
 // seed: from s_{T-1}: g_T = S s_{T-1}, s_T = C(g_T), lam_T = dL/ds_T,
 // eta_T = J_T^T lam_T, grad = rho0 [(dC/dF)^T lam_T + dL/dF]
 template <typename OffT>
@@ -740,15 +768,16 @@ __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const uint64_t own = a.tb.mask[t];
+    const TileRec rec = a.tb.rec[t];
+    const uint64_t own = rec.mask;
     const bool fl = lane_on(own);
-    const int slot = own_slot<true>(own, lane);
+    const Self<true, OffT> me(rec, lane);
     double eta[Q], gx = 0, gy = 0, gz = 0;
     if (fl) {
-        Nbhd h;
+        Nbhd<OffT> h;
         load_nbhd(h, a.tb, t);
         double g[Q];
-        gather_all<false, true, double, OffT>(g, h, a.s, t, lane, slot);
+        gather_all<false, true, double, OffT>(g, h, a.s, me, lane);
         double Fx, Fy, Fz;
         load_force<double>(a.P, t, lane, Fx, Fy, Fz);
         double s[Q];
@@ -769,7 +798,7 @@ __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
         collide_jt(g, lam, a.P.omega, a.P.kg, Fx, Fy, Fz, eta, gx, gy, gz);
         gx += -0.5 * irT * a.P.inv_nfluid;
     }
-    store_adjoint(reinterpret_cast<double *>(a.out) + (size_t)t * Q * TILE, own, fl, lane, slot, eta);
+    store_tile<double, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
     double *go = a.grad + (size_t)t * 3 * TILE + lane;
     go[0] = fl ? a.P.rho0 * gx : 0.0;
     go[TILE] = fl ? a.P.rho0 * gy : 0.0;
@@ -783,16 +812,17 @@ __global__ __launch_bounds__(512) void k_adj_step(AdjArgs a) {
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const uint64_t own = a.tb.mask[t];
+    const TileRec rec = a.tb.rec[t];
+    const uint64_t own = rec.mask;
     const bool fl = lane_on(own);
-    const int slot = own_slot<true>(own, lane);
+    const Self<true, OffT> me(rec, lane);
     double eta[Q];
     if (fl) {
-        Nbhd h;
+        Nbhd<OffT> h;
         load_nbhd(h, a.tb, t);
         double lam[Q], g[Q];
-        gather_all<true, true, double, OffT>(lam, h, a.eta_in, t, lane, slot);
-        gather_all<false, true, double, OffT>(g, h, a.s, t, lane, slot);
+        gather_all<true, true, double, OffT>(lam, h, a.eta_in, me, lane);
+        gather_all<false, true, double, OffT>(g, h, a.s, me, lane);
         double Fx, Fy, Fz;
         load_force<double>(a.P, t, lane, Fx, Fy, Fz);
         double gx, gy, gz;
@@ -802,7 +832,7 @@ __global__ __launch_bounds__(512) void k_adj_step(AdjArgs a) {
         go[TILE] += a.P.rho0 * gy;
         go[2 * TILE] += a.P.rho0 * gz;
     }
-    store_adjoint(reinterpret_cast<double *>(a.out) + (size_t)t * Q * TILE, own, fl, lane, slot, eta);
+    store_tile<double, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
 }
 
 // final: lam_0 = S^T eta_1
@@ -811,16 +841,17 @@ __global__ __launch_bounds__(512) void k_adj_final(AdjArgs a) {
     const int t = wave_tile();
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const uint64_t own = a.tb.mask[t];
+    const TileRec rec = a.tb.rec[t];
+    const uint64_t own = rec.mask;
     const bool fl = lane_on(own);
-    const int slot = own_slot<true>(own, lane);
+    const Self<true, OffT> me(rec, lane);
     double lam[Q];
     if (fl) {
-        Nbhd h;
+        Nbhd<OffT> h;
         load_nbhd(h, a.tb, t);
-        gather_all<true, true, double, OffT>(lam, h, a.eta_in, t, lane, slot);
+        gather_all<true, true, double, OffT>(lam, h, a.eta_in, me, lane);
     }
-    store_adjoint(reinterpret_cast<double *>(a.out) + (size_t)t * Q * TILE, own, fl, lane, slot, lam);
+    store_tile<double, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return lam[i]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -863,9 +894,9 @@ template <int ST, int KIND>
 static hipError_t calib_t(const Launch &L, const KArgs &a) {
     using C = Codec<ST>;
     if (L.off32)
-        hipLaunchKernelGGL((k_calib<typename C::S, C::PACKED, KIND, uint32_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
+        hipLaunchKernelGGL((k_calib<typename C::S, C::RUNS, KIND, uint32_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
     else
-        hipLaunchKernelGGL((k_calib<typename C::S, C::PACKED, KIND, uint64_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
+        hipLaunchKernelGGL((k_calib<typename C::S, C::RUNS, KIND, uint64_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
     return hipGetLastError();
 }
 

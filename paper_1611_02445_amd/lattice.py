@@ -75,7 +75,8 @@ class Lattice:
     and the reduction scratch, all allocated as torch tensors."""
 
     def __init__(self, solid, tau, periodic=0, rho0=1.0, storage="f64", model="qc", f16_log2_scale=20,
-                 tiles_per_wg=0, device="cuda", tiling=None, stream=None, f16_rounding="stochastic"):
+                 tiles_per_wg=0, device="cuda", tiling=None, stream=None, f16_rounding="stochastic",
+                 tile_order=0):
         import torch
 
         self.torch = torch
@@ -84,7 +85,8 @@ class Lattice:
         self.params = _abi.Params(tau=float(tau), rho0=float(rho0), storage=_abi.STORAGE[storage],
                                   model=_abi.MODEL[model], f16_log2_scale=int(f16_log2_scale),
                                   tiles_per_wg=int(tiles_per_wg),
-                                  f16_rounding={"stochastic": 0, "nearest": 1}[f16_rounding])
+                                  f16_rounding={"stochastic": 0, "nearest": 1}[f16_rounding],
+                                  tile_order=int(tile_order))
         self.storage = storage
         self.tau = float(tau)
         self.rho0 = float(rho0)
