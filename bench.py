@@ -122,6 +122,56 @@ def time_calib(solid, args, torch):
             "frac": gbs / HBM_PEAK_GBS, "fluid_nodes": nf, "tiles": lat.n_tiles}
 
 
+def time_adjoint(args, torch):
+    """Adjoint throughput on the 128^3 periodic sphere pack (porosity 0.5,
+    radius U[4,12), seed 4), FP64, tau 0.8, per-node g_x ~ N(1e-6, 1e-7),
+    T steps with checkpoints every K: MFLUPS of the reverse sweep with and
+    without the forward recomputation it needs."""
+    from paper_1611_02445_amd import inputs
+    from paper_1611_02445_amd.autograd import CheckpointedAdjoint
+    from paper_1611_02445_amd.lattice import Lattice
+    solid, _ = inputs.sphere_pack((128, 128, 128), 0.5, 4.0, 12.0, seed=4)
+    lat = Lattice(solid, 0.8, periodic=7, tiles_per_wg=args.tpw, tile_order=args.order)
+    rng = np.random.default_rng(40)
+    g = torch.zeros((3,) + lat.dense_shape, dtype=torch.float64)
+    g[0] = torch.from_numpy(rng.normal(1e-6, 1e-7, lat.dense_shape))
+    lat.set_force(g.cuda())
+    lat.init()
+    T, K = args.adj_steps, args.adj_k
+    run = CheckpointedAdjoint(lat, T, K)
+    run.forward(None)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(lat.stream)
+    run.backward()
+    ev[1].record(lat.stream)
+    torch.cuda.synchronize()
+    total_ms = ev[0].elapsed_time(ev[1])
+    # the adjoint kernels alone: T sweeps over ring buffers already filled
+    e_in, e_out = run.eta
+    s = run.ring[0]
+    ev[2].record(lat.stream)
+    lat.adjoint_seed(s, e_in, run.grad)
+    for _ in range(T - 1):
+        lat.adjoint_step(s, e_in, e_out, run.grad)
+        e_in, e_out = e_out, e_in
+    ev[3].record(lat.stream)
+    torch.cuda.synchronize()
+    kern_ms = ev[2].elapsed_time(ev[3])
+    nf = lat.n_fluid
+    out = {"workload": "128^3 sphere pack porosity 0.5, FP64, tau 0.8, per-node g_x ~ N(1e-6,1e-7)",
+           "T": T, "K": K, "fluid_nodes": nf, "memory_GB": round(run.memory_bytes() / 1e9, 2),
+           "MFLUPS_adjoint_kernels": round(nf * T / (kern_ms / 1e3) / 1e6, 1),
+           "MFLUPS_backward_incl_recompute": round(nf * T / (total_ms / 1e3) / 1e6, 1),
+           "recompute_steps": run.recompute_steps,
+           "bytes_per_fluid_update_adjoint": 3 * 19 * 8 + 48}
+    ms = kern_ms / T
+    out["adjoint_hbm_frac"] = round(out["bytes_per_fluid_update_adjoint"] * nf / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    log(f"[bench] adjoint: {out['MFLUPS_adjoint_kernels']} MFLUPS kernels, "
+        f"{out['MFLUPS_backward_incl_recompute']} MFLUPS incl. recompute")
+    return out
+
+
 def cpu_baseline(solid, args):
     """The oracle as it stands, on the same geometry, for a bounded number of
     steps (about --cpu-seconds of CPU work)."""
@@ -161,6 +211,8 @@ def main():
     ap.add_argument("--variants", default="f32,f16s", help="extra storage variants ('' for none)")
     ap.add_argument("--kernel", default="step", choices=["step", "rw", "prop"],
                     help="time the fused step, or the paper's read/write-only (rw) or propagation-only (prop) kernel")
+    ap.add_argument("--adj-steps", type=int, default=2000, help="adjoint horizon T (0 = skip the adjoint)")
+    ap.add_argument("--adj-k", type=int, default=100, help="adjoint checkpoint interval K")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -265,6 +317,9 @@ def main():
         result["variants"] = variants
     del r, lat
     torch.cuda.empty_cache()
+    if args.adj_steps > 0:
+        result["adjoint"] = time_adjoint(args, torch)
+        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")

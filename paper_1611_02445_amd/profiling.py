@@ -2,7 +2,7 @@
 
     python -m paper_1611_02445_amd.profiling trace   <trace_dir> <out.txt> <command...>
     python -m paper_1611_02445_amd.profiling counters <fetch_dir> <write_dir> <copy_fetch_dir> \
-        <copy_write_dir> <copy_bytes> <kernel_substring> <out.json> <command...>
+        <copy_write_dir> <copy_bytes> <kernel_substring> <grid_size|any> <out.json> <command...>
 
 ``trace`` turns a ``rocprofv3 --kernel-trace --stats -f csv`` directory into a
 per-kernel table (calls, average / min / max duration).  ``counters`` turns
@@ -40,39 +40,43 @@ def _find(d, pattern):
 
 
 def trace_table(trace_dir):
-    """{kernel name: (calls, avg_us, min_us, max_us)} from the kernel trace."""
+    """{(kernel name, grid size): (calls, avg_us, min_us, max_us)}: one kernel
+    launched on two workloads (different grids) gets two rows."""
     path = _find(trace_dir, "*kernel_trace.csv")
     d = defaultdict(list)
     with open(path) as fh:
         for r in csv.DictReader(fh):
-            d[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+            grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            d[(r["Kernel_Name"], grid)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     return {k: (len(v), sum(v) / len(v), min(v), max(v)) for k, v in d.items()}
 
 
 def trace_summary(trace_dir, command):
     rows = sorted(trace_table(trace_dir).items(), key=lambda kv: -kv[1][0] * kv[1][1])
     out = [f"# rocprofv3 kernel trace: {command}", "",
-           f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10}  kernel"]
-    for name, (n, avg, lo, hi) in rows:
-        out.append(f"{n:6d} {avg:10.2f} {lo:10.2f} {hi:10.2f}  {name}")
+           f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'grid':>10}  kernel"]
+    for (name, grid), (n, avg, lo, hi) in rows:
+        out.append(f"{n:6d} {avg:10.2f} {lo:10.2f} {hi:10.2f} {grid:10d}  {name}")
     return "\n".join(out) + "\n"
 
 
-def counter_per_dispatch(pmc_dir, counter, kernel_substring):
+def counter_per_dispatch(pmc_dir, counter, kernel_substring, grid=None):
     path = _find(pmc_dir, "*counter_collection.csv")
     vals = []
     with open(path) as fh:
         for r in csv.DictReader(fh):
-            if r["Counter_Name"] == counter and kernel_substring in r["Kernel_Name"]:
+            if r["Counter_Name"] == counter and kernel_substring in r["Kernel_Name"] and \
+                    (grid is None or int(r["Grid_Size"]) == grid):
                 vals.append(float(r["Counter_Value"]))
     if not vals:
         raise ValueError(f"no {counter} rows for kernels matching {kernel_substring!r} in {path}")
     return sum(vals) / len(vals), len(vals)
 
 
-def counters_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, kernel_substring, command):
-    fetch_kib, nf = counter_per_dispatch(fetch_dir, "FETCH_SIZE", kernel_substring)
-    write_kib, nw = counter_per_dispatch(write_dir, "WRITE_SIZE", kernel_substring)
+def counters_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, kernel_substring, command,
+                     grid=None):
+    fetch_kib, nf = counter_per_dispatch(fetch_dir, "FETCH_SIZE", kernel_substring, grid)
+    write_kib, nw = counter_per_dispatch(write_dir, "WRITE_SIZE", kernel_substring, grid)
     cfetch_kib, _ = counter_per_dispatch(cfetch_dir, "FETCH_SIZE", "copyBuffer")
     cwrite_kib, _ = counter_per_dispatch(cwrite_dir, "WRITE_SIZE", "copyBuffer")
     fs = copy_bytes / (cfetch_kib * 1024.0)
@@ -80,6 +84,7 @@ def counters_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, k
     hbm = fetch_kib * 1024.0 * fs + write_kib * 1024.0 * ws
     return {
         "kernel": kernel_substring,
+        "grid_size": grid,
         "kernel_source_hash": kernel_source_hash(),
         "command": command,
         "fetch_size_kib_per_dispatch": fetch_kib,
@@ -98,9 +103,10 @@ def main(argv):
         with open(argv[3], "w") as fh:
             fh.write(trace_summary(argv[2], " ".join(argv[4:])))
         return 0
-    if len(argv) >= 10 and argv[1] == "counters":
-        d = counters_summary(argv[2], argv[3], argv[4], argv[5], float(argv[6]), argv[7], " ".join(argv[9:]))
-        with open(argv[8], "w") as fh:
+    if len(argv) >= 11 and argv[1] == "counters":
+        grid = int(argv[8]) if argv[8] != "any" else None
+        d = counters_summary(argv[2], argv[3], argv[4], argv[5], float(argv[6]), argv[7], " ".join(argv[10:]), grid)
+        with open(argv[9], "w") as fh:
             json.dump(d, fh, indent=1)
         return 0
     print(__doc__, file=sys.stderr)
