@@ -172,6 +172,85 @@ def time_adjoint(args, torch):
     return out
 
 
+def time_pack1024(args, torch):
+    """The 1024x512x512 periodic sphere pack (porosity 0.2, radius U[6,16),
+    seed 5), FP32-shifted storage, tau 0.65, g_x 1e-5: 8000 forward steps, then
+    2000 more with checkpoints sized to the free HBM and the adjoint of those
+    2000; then FP64 against FP32 permeability on the 256^3 crop at the origin
+    (treated as periodic) after 10000 steps each."""
+    from paper_1611_02445_amd import inputs
+    from paper_1611_02445_amd.autograd import CheckpointedAdjoint
+    from paper_1611_02445_amd.lattice import Lattice
+    tau, g, T = 0.65, 1e-5, 2000
+    t0 = time.time()
+    solid, n_sph = inputs.sphere_pack((512, 512, 1024), 0.2, 6.0, 16.0, seed=5)
+    log(f"[bench] pack1024: spheres={n_sph} porosity={1 - solid.mean():.4f} ({time.time() - t0:.1f}s)")
+    lat = Lattice(solid, tau, periodic=7, storage="f32", tiles_per_wg=args.tpw, tile_order=args.order)
+    lat.init()
+    lat.set_force((g, 0.0, 0.0))
+    nf = lat.n_fluid
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    lat.step(20)
+    torch.cuda.synchronize()
+    ev[0].record(lat.stream)
+    lat.step(8000 - 20)
+    ev[1].record(lat.stream)
+    torch.cuda.synchronize()
+    fwd_ms = ev[0].elapsed_time(ev[1]) / (8000 - 20)
+    run = CheckpointedAdjoint.within_memory(lat, T)
+    ev[2].record(lat.stream)
+    L = run.forward(None)
+    ev[3].record(lat.stream)
+    run.backward(dense=False)
+    ev[4].record(lat.stream)
+    torch.cuda.synchronize()
+    ckpt_fwd_ms = ev[2].elapsed_time(ev[3])
+    back_ms = ev[3].elapsed_time(ev[4])
+    e_in, e_out = run.eta
+    s = run.ckpt[0]
+    ev[5].record(lat.stream)
+    lat.adjoint_seed(s, e_in, run.grad)
+    for _ in range(T - 1):
+        lat.adjoint_step(s, e_in, e_out, run.grad)
+        e_in, e_out = e_out, e_in
+    ev[6].record(lat.stream)
+    torch.cuda.synchronize()
+    kern_ms = ev[5].elapsed_time(ev[6])
+    out = {"workload": "1024x512x512 periodic sphere pack, porosity 0.2, radius U[6,16), seed 5; "
+                       "FP32-shifted storage, tau 0.65, g_x 1e-5; 10000 forward steps, adjoint of the last 2000",
+           "tiles": lat.n_tiles, "fluid_nodes": nf, "eta_t": round(lat.tiling.eta_t, 4),
+           "state_GB": round(lat.sizes.state_bytes / 1e9, 3),
+           "forward_MFLUPS": round(nf / (fwd_ms / 1e3) / 1e6, 1),
+           "forward_hbm_frac": round(BYTES_PER_UPDATE["f32"] * nf / (fwd_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+           "checkpointed_forward_MFLUPS": round(nf * T / (ckpt_fwd_ms / 1e3) / 1e6, 1),
+           "adjoint_T": T, "K": run.K, "K2": run.K2, "lattices": run.lattices(),
+           "memory_GB": round(run.memory_bytes() / 1e9, 1), "recompute_steps": run.recompute_steps,
+           "MFLUPS_adjoint_kernels": round(nf * T / (kern_ms / 1e3) / 1e6, 1),
+           "MFLUPS_backward_incl_recompute": round(nf * T / (back_ms / 1e3) / 1e6, 1),
+           "bytes_per_fluid_update_adjoint": 3 * 19 * 4 + 48,
+           "loss": L}
+    out["adjoint_hbm_frac"] = round(out["bytes_per_fluid_update_adjoint"] * nf / (kern_ms / T / 1e3) / 1e9
+                                    / HBM_PEAK_GBS, 4)
+    log(f"[bench] pack1024: forward {out['forward_MFLUPS']} MFLUPS, adjoint {out['MFLUPS_adjoint_kernels']} "
+        f"MFLUPS kernels, {out['MFLUPS_backward_incl_recompute']} incl. recompute (K={run.K}, K2={run.K2})")
+    del run, lat
+    torch.cuda.empty_cache()
+    crop = np.ascontiguousarray(solid[:256, :256, :256])
+    k = {}
+    for st in ("f64", "f32"):
+        lc = Lattice(crop, tau, periodic=7, storage=st)
+        lc.init()
+        lc.set_force((g, 0.0, 0.0))
+        lc.step(10000)
+        k[st] = lc.permeability(g)
+        del lc
+    out["crop256_permeability_f64"] = k["f64"]
+    out["crop256_permeability_f32"] = k["f32"]
+    out["crop256_rel_permeability_err"] = abs(k["f32"] - k["f64"]) / abs(k["f64"])
+    log(f"[bench] pack1024 crop: dk/k {out['crop256_rel_permeability_err']:.2e}")
+    return out
+
+
 def cpu_baseline(solid, args):
     """The oracle as it stands, on the same geometry, for a bounded number of
     steps (about --cpu-seconds of CPU work)."""
@@ -213,6 +292,8 @@ def main():
                     help="time the fused step, or the paper's read/write-only (rw) or propagation-only (prop) kernel")
     ap.add_argument("--adj-steps", type=int, default=2000, help="adjoint horizon T (0 = skip the adjoint)")
     ap.add_argument("--adj-k", type=int, default=100, help="adjoint checkpoint interval K")
+    ap.add_argument("--pack1024", action="store_true",
+                    help="also run the 1024x512x512 FP32 forward + adjoint workload (about 2 minutes)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -319,6 +400,9 @@ def main():
     torch.cuda.empty_cache()
     if args.adj_steps > 0:
         result["adjoint"] = time_adjoint(args, torch)
+        torch.cuda.empty_cache()
+    if args.pack1024:
+        result["pack1024"] = time_pack1024(args, torch)
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:

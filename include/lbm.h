@@ -110,11 +110,12 @@ typedef struct lbm_params {
 } lbm_params;
 
 typedef struct lbm_sizes {
-    size_t state_bytes;      /* one lattice: n_tiles * 19 * 64 * sizeof(storage) */
+    size_t state_bytes;      /* one lattice: per tile 19*k values (k fluid nodes) padded to whole
+                                128-byte lines (FP64, FP32); n_tiles * 19 * 64 * 2 (FP16) */
     size_t table_bytes;      /* device copy of the tiling tables */
     size_t scratch_bytes;    /* reduction scratch */
     size_t force_bytes;      /* per-node force field in tile order: n_tiles * 3 * 64 * sizeof(arith) */
-    size_t adjoint_bytes;    /* one adjoint lattice: n_tiles * 19 * 64 * sizeof(arith) */
+    size_t adjoint_bytes;    /* one adjoint lattice: state_bytes (FP64, FP32), 0 for FP16 */
     size_t grad_force_bytes; /* force gradient, FP64: n_tiles * 3 * 64 * 8 */
     size_t dense_nodes;      /* nx * ny * nz of the padded box */
 } lbm_sizes;
@@ -196,7 +197,9 @@ int lbm_set_state(lbm_ctx *ctx, const double *f_dense_dev, void *state);
 int lbm_tiles_to_dense(lbm_ctx *ctx, const void *tile_buf, int32_t ncomp, int32_t dtype, double *dense_dev);
 
 /* ------------------------------------------------------------------------
- * Discrete adjoint (quasi-compressible model, FP64 storage).
+ * Discrete adjoint (quasi-compressible model; FP64 storage with FP64
+ * arithmetic, or FP32 storage with FP32 arithmetic; FP16 storage returns
+ * LBM_E_UNSUPPORTED).
  *
  * Forward: s_t = C(S s_{t-1}, F), S = pull streaming with bounce-back,
  * C = local LBGK + Guo collision.  Loss L = (1/N_fluid) sum_fluid u_x(s_T).
@@ -208,10 +211,19 @@ int lbm_tiles_to_dense(lbm_ctx *ctx, const void *tile_buf, int32_t ncomp, int32_
  *     lbm_adjoint_seed(s_{T-1})                      -> eta_T,  gF  = ...
  *     lbm_adjoint_step(s_{t-2}, eta_t) for t=T..2   -> eta_{t-1}, gF += ...
  *     lbm_adjoint_final(eta_1)                        -> lambda_0 = dL/ds_0
+ * An adjoint lattice (adjoint_bytes, caller-owned device memory) has the
+ * layout and element type of the state but holds unshifted values: the
+ * shift of reduced storage is a constant, so dL/dd = dL/df.  Forward states
+ * are the context's own lattices or buffers of state_bytes.  All calls are
+ * asynchronous on the context's stream.
  * ------------------------------------------------------------------------ */
 int lbm_adjoint_seed(lbm_ctx *ctx, const void *s_Tm1, void *eta_T, double *grad_g_tile);
 int lbm_adjoint_step(lbm_ctx *ctx, const void *s_tm2, const void *eta_t, void *eta_tm1, double *grad_g_tile);
 int lbm_adjoint_final(lbm_ctx *ctx, const void *eta_1, void *lambda_0);
+/* Dense FP64 copy [19][nz][ny][nx] (device) of an adjoint lattice, and the
+ * reverse; 0 at solid and dropped nodes / solid slots set to 0. */
+int lbm_adjoint_get(lbm_ctx *ctx, const void *adj, double *dense_dev);
+int lbm_adjoint_set(lbm_ctx *ctx, const double *dense_dev, void *adj);
 
 /* ------------------------------------------------------------------------
  * Measurement kernels (the paper's "read/write only" and "propagation only"

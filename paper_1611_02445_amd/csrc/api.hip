@@ -125,7 +125,9 @@ extern "C" int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *para
     out->table_bytes = TableLayout((int64_t)n).total;
     out->scratch_bytes = (n + 1) * NSUM * sizeof(double);
     out->force_bytes = n * 3 * TILE * arith_size(params->storage);
-    out->adjoint_bytes = lattice_elems(tiles, LBM_F64) * 8;  // FP64 runs, as the FP64 lattice
+    // the adjoint lattice has the layout and element type of the state (runs);
+    // FP16 storage has no adjoint
+    out->adjoint_bytes = params->storage == LBM_F16S ? 0 : out->state_bytes;
     out->grad_force_bytes = n * 3 * TILE * sizeof(double);
     out->dense_nodes = (size_t)tiles->nx * (size_t)tiles->ny * (size_t)tiles->nz;
     return LBM_OK;
@@ -385,10 +387,36 @@ extern "C" int lbm_tiles_to_dense(lbm_ctx *c, const void *tile_buf, int32_t ncom
 }
 
 static int adjoint_supported(lbm_ctx *c) {
-    if (c->params.storage != LBM_F64) return fail(LBM_E_UNSUPPORTED, "adjoint: only FP64 storage is built");
+    if (c->params.storage == LBM_F16S) return fail(LBM_E_UNSUPPORTED, "adjoint: built for FP64 and FP32 storage only");
     if (c->params.model != LBM_QUASI_COMPRESSIBLE)
         return fail(LBM_E_UNSUPPORTED, "adjoint: only the quasi-compressible model is built");
     return LBM_OK;
+}
+
+// adjoint lattices hold unshifted values: the state codec with no shift
+static Phys unshifted(const lbm_ctx *c) {
+    Phys P = c->P;
+    P.rho_base = 0.0;
+    return P;
+}
+
+extern "C" int lbm_adjoint_get(lbm_ctx *c, const void *adj, double *dense_dev) {
+    CHECK_CTX(c);
+    int rc = adjoint_supported(c);
+    if (rc) return rc;
+    if (!dense_dev || (!adj && c->n_tiles > 0)) return fail(LBM_E_INVAL, "lbm_adjoint_get: NULL buffer");
+    const size_t N = (size_t)c->nx * c->ny * c->nz;
+    hipError_t e = launch_fill(c->stream, dense_dev, Q * N);
+    if (e == hipSuccess) e = launch_get_state(c->L, unshifted(c), adj, dense_dev, c->nx, c->ny, c->nz);
+    return launched(e, "lbm_adjoint_get");
+}
+
+extern "C" int lbm_adjoint_set(lbm_ctx *c, const double *dense_dev, void *adj) {
+    CHECK_CTX(c);
+    int rc = adjoint_supported(c);
+    if (rc) return rc;
+    if (!dense_dev || (!adj && c->n_tiles > 0)) return fail(LBM_E_INVAL, "lbm_adjoint_set: NULL buffer");
+    return launched(launch_set_state(c->L, unshifted(c), dense_dev, adj, c->nx, c->ny, c->nz), "lbm_adjoint_set");
 }
 
 extern "C" int lbm_adjoint_seed(lbm_ctx *c, const void *s_Tm1, void *eta_T, double *grad_g_tile) {

@@ -98,10 +98,12 @@ __device__ __forceinline__ int remap_block(int b, int nb) {
     return xcd * q + (xcd < r ? xcd : r) + local;
 }
 
-__device__ __forceinline__ int wave_tile() {
+// wpb (waves per workgroup) and nb (workgroups) come in as kernel arguments:
+// reading blockDim from the dispatch packet would cost every wave a memory
+// round trip before its first instruction of real work.
+__device__ __forceinline__ int wave_tile(int wpb, int nb) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int wpb = (int)(blockDim.x >> 6);
-    return remap_block((int)blockIdx.x, (int)gridDim.x) * wpb + wave;
+    return remap_block((int)blockIdx.x, nb) * wpb + wave;
 }
 
 __device__ __forceinline__ bool lane_on(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
@@ -222,11 +224,16 @@ __device__ __forceinline__ OffT region_elem(const Nbhd<OffT> &h, int lane) {
     }
 }
 
+// computed for every lane and then selected (a lane select, not a branch)
 template <int SX, int SY, int SZ, int BX, int BY, int BZ, int I, bool RUNS, typename OffT>
 __device__ __forceinline__ OffT region_pick(const Nbhd<OffT> &h, int lane, OffT cur) {
     using R = Region<SX, SY, SZ, BX, BY, BZ>;
-    if constexpr (!R::EXISTS) return cur;
-    else return lane_on(R::LANES) ? region_elem<R, I, RUNS, OffT>(h, lane) : cur;
+    if constexpr (!R::EXISTS) {
+        return cur;
+    } else {
+        const OffT mine = region_elem<R, I, RUNS, OffT>(h, lane);
+        return lane_on(R::LANES) ? mine : cur;
+    }
 }
 
 template <typename OffT, typename S>
@@ -377,6 +384,8 @@ struct KArgs {
     char *dst;
     DevTables tb;
     int n_tiles;
+    int wpb;      // waves (tiles) per workgroup
+    int nblocks;  // workgroups in the grid
     Phys P;
 };
 
@@ -404,7 +413,7 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
     using S = typename C::S;
     using T = typename C::T;
     constexpr bool RN = C::RUNS;
-    const int t = wave_tile();
+    const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const TileRec rec = a.tb.rec[t];
@@ -443,7 +452,7 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
 // kind 2 "propagation only"
 template <typename S, bool RN, int KIND, typename OffT>
 __global__ __launch_bounds__(512) void k_calib(KArgs a) {
-    const int t = wave_tile();
+    const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const TileRec rec = a.tb.rec[t];
@@ -472,7 +481,7 @@ template <int ST>
 __global__ __launch_bounds__(512) void k_init(KArgs a, char *b, double ux, double uy, double uz) {
     using C = Codec<ST>;
     using S = typename C::S;
-    const int t = wave_tile();
+    const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const TileRec rec = a.tb.rec[t];
@@ -531,7 +540,7 @@ __global__ __launch_bounds__(512) void k_macro(KArgs a, double *rho_out, double 
     using C = Codec<ST>;
     using S = typename C::S;
     using T = typename C::T;
-    const int t = wave_tile();
+    const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const TileRec rec = a.tb.rec[t];
@@ -626,7 +635,7 @@ template <int ST>
 __global__ __launch_bounds__(512) void k_get_state(KArgs a, double *dense, int nx, int ny, int nz) {
     using C = Codec<ST>;
     using S = typename C::S;
-    const int t = wave_tile();
+    const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const TileRec rec = a.tb.rec[t];
@@ -645,7 +654,7 @@ __global__ __launch_bounds__(512) void k_set_state(KArgs a, const double *dense,
     using C = Codec<ST>;
     using S = typename C::S;
     using T = typename C::T;
-    const int t = wave_tile();
+    const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const TileRec rec = a.tb.rec[t];
@@ -667,7 +676,7 @@ __global__ __launch_bounds__(512) void k_set_state(KArgs a, const double *dense,
 
 template <typename T>
 __global__ __launch_bounds__(512) void k_force_to_tiles(KArgs a, const double *g, T *out, int nx, int ny, int nz) {
-    const int t = wave_tile();
+    const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const bool fl = (a.tb.rec[t].mask >> lane) & 1;
@@ -681,7 +690,7 @@ __global__ __launch_bounds__(512) void k_force_to_tiles(KArgs a, const double *g
 template <typename T>
 __global__ __launch_bounds__(512) void k_tiles_to_dense(KArgs a, const T *in, int ncomp, double *dense, int nx, int ny,
                                                        int nz) {
-    const int t = wave_tile();
+    const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const bool fl = (a.tb.rec[t].mask >> lane) & 1;
@@ -691,7 +700,8 @@ __global__ __launch_bounds__(512) void k_tiles_to_dense(KArgs a, const T *in, in
 }
 
 // ---------------------------------------------------------------------------
-// discrete adjoint (quasi-compressible, FP64, runs layout)
+// discrete adjoint (quasi-compressible, runs layout; FP64 storage with FP64
+// arithmetic or FP32 storage with FP32 arithmetic, gradient sums in FP64)
 //
 // For the local collision C(g, F) with rho = sum g, u = (sum c g + F/2)/rho:
 //   (J^T lam)_j = (1 - 1/tau) lam_j + A + V.(c_j - u)/rho
@@ -700,55 +710,59 @@ __global__ __launch_bounds__(512) void k_tiles_to_dense(KArgs a, const T *in, in
 //                       + kg w_i (9 (c_i.F) c_i - 3 F) ]
 //   (dC/dF)^T lam = V/(2 rho) + kg sum_i lam_i w_i (3 (c_i - u) + 9 (c_i.u) c_i)
 // computed with the sums p = sum lam w (rho/tau (3 + 9 c.u) + 9 kg c.F) c,
-// r = sum lam w (3 + 9 c.u) c and q = sum lam w.
+// r = sum lam w (3 + 9 c.u) c and q = sum lam w.  J depends on g only through
+// rho and j = sum c g, so the forward values may be the shifted ones
+// d = g - w rho_base (rho = rho_base + sum d, j = sum c d).  The adjoint
+// values themselves are never shifted.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void collide_jt(const double (&g)[Q], const double (&lam)[Q], double omega, double kg,
-                                           double Fx, double Fy, double Fz, double (&eta)[Q], double &gx,
-                                           double &gy, double &gz) {
-    double rho = 0, jx = 0, jy = 0, jz = 0;
+template <typename T>
+__device__ __forceinline__ void collide_jt(const T (&d)[Q], T rho_base, const T (&lam)[Q], T omega, T kg, T Fx, T Fy,
+                                           T Fz, T (&eta)[Q], T &gx, T &gy, T &gz) {
+    T drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        rho += g[i];
-        jx += CX[i] * g[i];
-        jy += CY[i] * g[i];
-        jz += CZ[i] * g[i];
+        drho += d[i];
+        jx += T(CX[i]) * d[i];
+        jy += T(CY[i]) * d[i];
+        jz += T(CZ[i]) * d[i];
     }
-    const double ir = 1.0 / rho;
-    const double ux = (jx + 0.5 * Fx) * ir, uy = (jy + 0.5 * Fy) * ir, uz = (jz + 0.5 * Fz) * ir;
-    const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
-    const double ro = rho * omega;
-    double A = 0, q = 0, px = 0, py = 0, pz = 0, rx = 0, ry = 0, rz = 0;
+    const T rho = rho_base + drho;
+    const T ir = T(1) / rho;
+    const T ux = (jx + T(0.5) * Fx) * ir, uy = (jy + T(0.5) * Fy) * ir, uz = (jz + T(0.5) * Fz) * ir;
+    const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
+    const T ro = rho * omega;
+    T A = 0, q = 0, px = 0, py = 0, pz = 0, rx = 0, ry = 0, rz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const double w = weight(i);
-        const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-        const double cF = CX[i] * Fx + CY[i] * Fy + CZ[i] * Fz;
-        const double lw = lam[i] * w;
-        A += lw * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq);
+        const T w = T(weight(i));
+        const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
+        const T cF = T(CX[i]) * Fx + T(CY[i]) * Fy + T(CZ[i]) * Fz;
+        const T lw = lam[i] * w;
+        A += lw * (T(1) + T(3) * cu + T(4.5) * cu * cu - usq);
         q += lw;
-        const double a3 = 3.0 + 9.0 * cu;
-        const double pi = lw * (ro * a3 + 9.0 * kg * cF);
-        const double ri = lw * a3;
-        px += CX[i] * pi;
-        py += CY[i] * pi;
-        pz += CZ[i] * pi;
-        rx += CX[i] * ri;
-        ry += CY[i] * ri;
-        rz += CZ[i] * ri;
+        const T a3 = T(3) + T(9) * cu;
+        const T pi = lw * (ro * a3 + T(9) * kg * cF);
+        const T ri = lw * a3;
+        px += T(CX[i]) * pi;
+        py += T(CY[i]) * pi;
+        pz += T(CZ[i]) * pi;
+        rx += T(CX[i]) * ri;
+        ry += T(CY[i]) * ri;
+        rz += T(CZ[i]) * ri;
     }
     A *= omega;
-    const double Vx = px - q * (3.0 * ro * ux + 3.0 * kg * Fx);
-    const double Vy = py - q * (3.0 * ro * uy + 3.0 * kg * Fy);
-    const double Vz = pz - q * (3.0 * ro * uz + 3.0 * kg * Fz);
-    const double Vu = Vx * ux + Vy * uy + Vz * uz;
+    const T Vx = px - q * (T(3) * ro * ux + T(3) * kg * Fx);
+    const T Vy = py - q * (T(3) * ro * uy + T(3) * kg * Fy);
+    const T Vz = pz - q * (T(3) * ro * uz + T(3) * kg * Fz);
+    const T Vu = Vx * ux + Vy * uy + Vz * uz;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-        const double Vc = CX[j] * Vx + CY[j] * Vy + CZ[j] * Vz;
-        eta[j] = (1.0 - omega) * lam[j] + A + (Vc - Vu) * ir;
+        const T Vc = T(CX[j]) * Vx + T(CY[j]) * Vy + T(CZ[j]) * Vz;
+        eta[j] = (T(1) - omega) * lam[j] + A + (Vc - Vu) * ir;
     }
-    gx = 0.5 * Vx * ir + kg * (rx - 3.0 * q * ux);
-    gy = 0.5 * Vy * ir + kg * (ry - 3.0 * q * uy);
-    gz = 0.5 * Vz * ir + kg * (rz - 3.0 * q * uz);
+    gx = T(0.5) * Vx * ir + kg * (rx - T(3) * q * ux);
+    gy = T(0.5) * Vy * ir + kg * (ry - T(3) * q * uy);
+    gz = T(0.5) * Vz * ir + kg * (rz - T(3) * q * uz);
 }
 
 struct AdjArgs {
@@ -758,100 +772,106 @@ struct AdjArgs {
     double *grad;       // [n_tiles][3][64] FP64 (lane order), dL/dg
     DevTables tb;
     int n_tiles;
+    int wpb;
+    int nblocks;
     Phys P;
 };
 
 // seed: from s_{T-1}: g_T = S s_{T-1}, s_T = C(g_T), lam_T = dL/ds_T,
 // eta_T = J_T^T lam_T, grad = rho0 [(dC/dF)^T lam_T + dL/dF]
-template <typename OffT>
+template <int ST, typename OffT>
 __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
-    const int t = wave_tile();
+    using T = typename Codec<ST>::S;
+    const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const TileRec rec = a.tb.rec[t];
     const uint64_t own = rec.mask;
     const bool fl = lane_on(own);
     const Self<true, OffT> me(rec, lane);
-    double eta[Q], gx = 0, gy = 0, gz = 0;
+    const T rb = T(a.P.rho_base), om = T(a.P.omega), kg = T(a.P.kg), inv_n = T(a.P.inv_nfluid);
+    T eta[Q], gx = 0, gy = 0, gz = 0;
     if (fl) {
         Nbhd<OffT> h;
         load_nbhd(h, a.tb, t);
-        double g[Q];
-        gather_all<false, true, double, OffT>(g, h, a.s, me, lane);
-        double Fx, Fy, Fz;
-        load_force<double>(a.P, t, lane, Fx, Fy, Fz);
-        double s[Q];
+        T g[Q];
+        gather_all<false, true, T, OffT>(g, h, a.s, me, lane);
+        T Fx, Fy, Fz;
+        load_force<T>(a.P, t, lane, Fx, Fy, Fz);
+        T s[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) s[i] = g[i];
-        collide<double, LBM_QUASI_COMPRESSIBLE>(s, 0.0, a.P.omega, a.P.kg, Fx, Fy, Fz);
-        double rT = 0, jx = 0;
+        collide<T, LBM_QUASI_COMPRESSIBLE>(s, rb, om, kg, Fx, Fy, Fz);
+        T drT = 0, jx = 0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            rT += s[i];
-            jx += CX[i] * s[i];
+            drT += s[i];
+            jx += T(CX[i]) * s[i];
         }
-        const double irT = 1.0 / rT;
-        const double uxT = (jx - 0.5 * Fx) * irT;
-        double lam[Q];
+        const T irT = T(1) / (rb + drT);
+        const T uxT = (jx - T(0.5) * Fx) * irT;
+        T lam[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) lam[i] = (CX[i] - uxT) * irT * a.P.inv_nfluid;
-        collide_jt(g, lam, a.P.omega, a.P.kg, Fx, Fy, Fz, eta, gx, gy, gz);
-        gx += -0.5 * irT * a.P.inv_nfluid;
+        for (int i = 0; i < Q; ++i) lam[i] = (T(CX[i]) - uxT) * irT * inv_n;
+        collide_jt<T>(g, rb, lam, om, kg, Fx, Fy, Fz, eta, gx, gy, gz);
+        gx += T(-0.5) * irT * inv_n;
     }
-    store_tile<double, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
+    store_tile<T, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
     double *go = a.grad + (size_t)t * 3 * TILE + lane;
-    go[0] = fl ? a.P.rho0 * gx : 0.0;
-    go[TILE] = fl ? a.P.rho0 * gy : 0.0;
-    go[2 * TILE] = fl ? a.P.rho0 * gz : 0.0;
+    go[0] = fl ? a.P.rho0 * (double)gx : 0.0;
+    go[TILE] = fl ? a.P.rho0 * (double)gy : 0.0;
+    go[2 * TILE] = fl ? a.P.rho0 * (double)gz : 0.0;
 }
 
 // step: lam_{t-1} = S^T eta_t (reverse gather), g_{t-1} = S s_{t-2},
 // eta_{t-1} = J^T lam_{t-1}, grad += rho0 (dC/dF)^T lam_{t-1}
-template <typename OffT>
+template <int ST, typename OffT>
 __global__ __launch_bounds__(512) void k_adj_step(AdjArgs a) {
-    const int t = wave_tile();
+    using T = typename Codec<ST>::S;
+    const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const TileRec rec = a.tb.rec[t];
     const uint64_t own = rec.mask;
     const bool fl = lane_on(own);
     const Self<true, OffT> me(rec, lane);
-    double eta[Q];
+    T eta[Q];
     if (fl) {
         Nbhd<OffT> h;
         load_nbhd(h, a.tb, t);
-        double lam[Q], g[Q];
-        gather_all<true, true, double, OffT>(lam, h, a.eta_in, me, lane);
-        gather_all<false, true, double, OffT>(g, h, a.s, me, lane);
-        double Fx, Fy, Fz;
-        load_force<double>(a.P, t, lane, Fx, Fy, Fz);
-        double gx, gy, gz;
-        collide_jt(g, lam, a.P.omega, a.P.kg, Fx, Fy, Fz, eta, gx, gy, gz);
+        T lam[Q], g[Q];
+        gather_all<true, true, T, OffT>(lam, h, a.eta_in, me, lane);
+        gather_all<false, true, T, OffT>(g, h, a.s, me, lane);
+        T Fx, Fy, Fz;
+        load_force<T>(a.P, t, lane, Fx, Fy, Fz);
+        T gx, gy, gz;
+        collide_jt<T>(g, T(a.P.rho_base), lam, T(a.P.omega), T(a.P.kg), Fx, Fy, Fz, eta, gx, gy, gz);
         double *go = a.grad + (size_t)t * 3 * TILE + lane;
-        go[0] += a.P.rho0 * gx;
-        go[TILE] += a.P.rho0 * gy;
-        go[2 * TILE] += a.P.rho0 * gz;
+        go[0] += a.P.rho0 * (double)gx;
+        go[TILE] += a.P.rho0 * (double)gy;
+        go[2 * TILE] += a.P.rho0 * (double)gz;
     }
-    store_tile<double, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
+    store_tile<T, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
 }
 
 // final: lam_0 = S^T eta_1
-template <typename OffT>
+template <int ST, typename OffT>
 __global__ __launch_bounds__(512) void k_adj_final(AdjArgs a) {
-    const int t = wave_tile();
+    using T = typename Codec<ST>::S;
+    const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const TileRec rec = a.tb.rec[t];
     const uint64_t own = rec.mask;
     const bool fl = lane_on(own);
     const Self<true, OffT> me(rec, lane);
-    double lam[Q];
+    T lam[Q];
     if (fl) {
         Nbhd<OffT> h;
         load_nbhd(h, a.tb, t);
-        gather_all<true, true, double, OffT>(lam, h, a.eta_in, me, lane);
+        gather_all<true, true, T, OffT>(lam, h, a.eta_in, me, lane);
     }
-    store_tile<double, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return lam[i]; });
+    store_tile<T, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return lam[i]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -863,6 +883,8 @@ static KArgs make_args(const Launch &L, const Phys &P, const void *src, void *ds
     a.dst = reinterpret_cast<char *>(dst);
     a.tb = L.tb;
     a.n_tiles = L.n_tiles;
+    a.wpb = L.tpw;
+    a.nblocks = L.grid;
     a.P = P;
     return a;
 }
@@ -1002,39 +1024,48 @@ static AdjArgs make_adj(const Launch &L, const Phys &P, const void *s, const voi
     a.grad = grad;
     a.tb = L.tb;
     a.n_tiles = L.n_tiles;
+    a.wpb = L.tpw;
+    a.nblocks = L.grid;
     a.P = P;
     return a;
 }
 
-hipError_t launch_adjoint_seed(const Launch &L, const Phys &P, const void *s_prev, void *eta, double *grad) {
+// the adjoint kernels exist for FP64 and FP32 storage (runs layout)
+template <int ST, typename OffT>
+struct SeedK {
+    static constexpr auto fn = k_adj_seed<ST, OffT>;
+};
+template <int ST, typename OffT>
+struct StepK {
+    static constexpr auto fn = k_adj_step<ST, OffT>;
+};
+template <int ST, typename OffT>
+struct FinalK {
+    static constexpr auto fn = k_adj_final<ST, OffT>;
+};
+
+template <template <int, typename> class K>
+static hipError_t launch_adj(const Launch &L, const AdjArgs &a) {
     if (L.n_tiles == 0) return hipSuccess;
-    const AdjArgs a = make_adj(L, P, s_prev, nullptr, eta, grad);
-    if (L.off32)
-        hipLaunchKernelGGL(k_adj_seed<uint32_t>, dim3(L.grid), block_of(L), 0, L.stream, a);
-    else
-        hipLaunchKernelGGL(k_adj_seed<uint64_t>, dim3(L.grid), block_of(L), 0, L.stream, a);
+    const bool f32 = a.P.storage == LBM_F32;
+    void (*fn)(AdjArgs);
+    if (L.off32) fn = f32 ? K<LBM_F32, uint32_t>::fn : K<LBM_F64, uint32_t>::fn;
+    else fn = f32 ? K<LBM_F32, uint64_t>::fn : K<LBM_F64, uint64_t>::fn;
+    hipLaunchKernelGGL(fn, dim3(L.grid), block_of(L), 0, L.stream, a);
     return hipGetLastError();
+}
+
+hipError_t launch_adjoint_seed(const Launch &L, const Phys &P, const void *s_prev, void *eta, double *grad) {
+    return launch_adj<SeedK>(L, make_adj(L, P, s_prev, nullptr, eta, grad));
 }
 
 hipError_t launch_adjoint_step(const Launch &L, const Phys &P, const void *s_prev2, const void *eta_in, void *eta_out,
                                double *grad) {
-    if (L.n_tiles == 0) return hipSuccess;
-    const AdjArgs a = make_adj(L, P, s_prev2, eta_in, eta_out, grad);
-    if (L.off32)
-        hipLaunchKernelGGL(k_adj_step<uint32_t>, dim3(L.grid), block_of(L), 0, L.stream, a);
-    else
-        hipLaunchKernelGGL(k_adj_step<uint64_t>, dim3(L.grid), block_of(L), 0, L.stream, a);
-    return hipGetLastError();
+    return launch_adj<StepK>(L, make_adj(L, P, s_prev2, eta_in, eta_out, grad));
 }
 
 hipError_t launch_adjoint_final(const Launch &L, const Phys &P, const void *eta_in, void *lambda_out) {
-    if (L.n_tiles == 0) return hipSuccess;
-    const AdjArgs a = make_adj(L, P, nullptr, eta_in, lambda_out, nullptr);
-    if (L.off32)
-        hipLaunchKernelGGL(k_adj_final<uint32_t>, dim3(L.grid), block_of(L), 0, L.stream, a);
-    else
-        hipLaunchKernelGGL(k_adj_final<uint64_t>, dim3(L.grid), block_of(L), 0, L.stream, a);
-    return hipGetLastError();
+    return launch_adj<FinalK>(L, make_adj(L, P, nullptr, eta_in, lambda_out, nullptr));
 }
 
 }  // namespace tlbm

@@ -225,6 +225,21 @@ class Lattice:
     def adjoint_final(self, eta_1, lambda_0):
         call("lbm_adjoint_final", self.ctx, _vp(eta_1), _vp(lambda_0))
 
+    def adjoint_get(self, adj):
+        """Dense FP64 [19, nz, ny, nx] copy of an adjoint lattice."""
+        torch = self.torch
+        out = torch.empty((19,) + self.dense_shape, dtype=torch.float64, device=self.device)
+        call("lbm_adjoint_get", self.ctx, _vp(adj), _vp(out))
+        return out
+
+    def adjoint_set(self, dense, adj):
+        torch = self.torch
+        v = torch.as_tensor(dense).to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(v.shape) != (19,) + self.dense_shape:
+            raise ValueError(f"adjoint lattice must have shape {(19,) + self.dense_shape}")
+        call("lbm_adjoint_set", self.ctx, _vp(v), _vp(adj))
+        self.stream.synchronize()
+
     def info(self):
         n_t, n_f, st, gb = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
         call("lbm_info", self.ctx, ctypes.byref(n_t), ctypes.byref(n_f), ctypes.byref(st), ctypes.byref(gb))

@@ -156,3 +156,114 @@ def test_adjoint_full_size_finite_differences():
             log(f"   f node {n} i {i}: fd {fd:.10e} adjoint {ad:.10e} rel {rel:.2e}")
             assert rel <= 1e-6
     log(f"   L {L0:.6e}; worst g rel err {worst:.2e}")
+
+
+# FP32 storage and arithmetic (gradients still summed in FP64).  Each adjoint
+# step evaluates every value with O(Q) FP32 operations, so its rounding is a
+# few Q * 2^-24 of the largest adjoint value; over T steps the errors add up:
+# bound T * Q * 2^-24 * 8 relative to the largest gradient entry.
+F32_EPS = 2.0 ** -24
+
+
+@pytest.mark.parametrize("periodic,K,K2", [(7, 5, None), (0, 6, 2)])
+def test_adjoint_f32_matches_oracle(periodic, K, K2):
+    import torch
+    from paper_1611_02445_amd.autograd import CheckpointedAdjoint
+    tau, T = 0.8, 12
+    s, _ = I.sphere_pack((12, 16, 12), 0.55, 2.0, 3.5, seed=22, periodic=bool(periodic & 1))
+    sp = padded(s, periodic)
+    f0 = perturbed_state(sp, 5)
+    g = _force_field(sp, 6)
+    log(f"[case] f32 adjoint vs oracle periodic={periodic} K={K} K2={K2} T={T}")
+    Lo, gs_o, gF_o = O.adjoint(f0, sp, tau, g, T, periodic=periodic)
+    lat = new_lattice(s, tau, periodic, storage="f32")
+    lat.set_force(torch.from_numpy(g).cuda())
+    run = CheckpointedAdjoint(lat, T, K, K2)
+    L = run.forward(torch.from_numpy(f0))
+    gs, gg = run.backward()
+    gs, gg = gs.cpu().numpy(), gg.cpu().numpy()
+    fl = sp == 0
+    tol = T * 19 * F32_EPS * 8
+    es = np.max(np.abs(gs[:, fl] - gs_o[:, fl])) / np.abs(gs_o[:, fl]).max()
+    eg = np.max(np.abs(gg[:, fl] - gF_o[:, fl])) / np.abs(gF_o[:, fl]).max()
+    # the loss is a mean of u_x; each u_x carries at most the same relative
+    # rounding bound times max|u|
+    rho, u, _ = O.macroscopic(O.run(f0, sp, tau, g, T, periodic=periodic), sp, g)
+    umax = np.abs(u[:, fl]).max()
+    log(f"   L {L:.9e} vs {Lo:.9e} (tol {tol * umax:.2e});  dL/ds0 err {es:.2e}  dL/dg err {eg:.2e}  tol {tol:.2e}")
+    assert abs(L - Lo) <= tol * umax
+    assert es <= tol and eg <= tol
+    assert np.all(gs[:, ~fl] == 0) and np.all(gg[:, ~fl] == 0)
+
+
+def test_reverse_gather_is_transpose_of_pull_f32():
+    """FP32 adjoint lattices: the reverse gather and the propagation-only
+    kernel move values without arithmetic, so both match the oracle's S and
+    S^T exactly on FP32-representable inputs."""
+    import torch
+    s, _ = I.sphere_pack((16, 16, 16), 0.5, 2.0, 4.0, seed=32)
+    sp = padded(s, 7)
+    fl = (sp == 0)[None]
+    rng = np.random.default_rng(8)
+    v = (rng.normal(size=(19,) + sp.shape) * fl).astype(np.float32).astype(np.float64)
+    w = (rng.normal(size=(19,) + sp.shape) * fl).astype(np.float32).astype(np.float64)
+    lat = new_lattice(s, 0.8, 7, storage="f32")
+    a, b = lat.new_adjoint(), lat.new_adjoint()
+    lat.adjoint_set(torch.from_numpy(v), a)
+    assert np.array_equal(lat.adjoint_get(a).cpu().numpy(), v)
+    lat.calib_step(2, a, b)
+    assert np.array_equal(lat.adjoint_get(b).cpu().numpy(), O.pull(v, sp, periodic=7))
+    lat.adjoint_set(torch.from_numpy(w), a)
+    lat.adjoint_final(a, b)
+    assert np.array_equal(lat.adjoint_get(b).cpu().numpy(), O.pull_transpose(w, sp, periodic=7))
+
+
+def test_two_level_schedule_is_bitwise_one_level():
+    """The schedule only changes which forward states are recomputed when;
+    the kernels are deterministic, so the gradients are bitwise equal."""
+    import torch
+    from paper_1611_02445_amd.autograd import CheckpointedAdjoint
+    tau, T = 0.7, 29
+    s, _ = I.sphere_pack((16, 16, 20), 0.5, 2.0, 4.0, seed=51)
+    sp = padded(s, 7)
+    f0 = torch.from_numpy(perturbed_state(sp, 9))
+    g = torch.from_numpy(_force_field(sp, 10)).cuda()
+    out = []
+    for K, K2 in ((5, None), (29, None), (10, 3), (12, 5)):
+        lat = new_lattice(s, tau, 7)
+        lat.set_force(g)
+        run = CheckpointedAdjoint(lat, T, K, K2)
+        L = run.forward(f0)
+        gs, gg = run.backward()
+        out.append((L, gs.cpu().numpy(), gg.cpu().numpy()))
+    for L, gs, gg in out[1:]:
+        assert L == out[0][0]
+        assert np.array_equal(gs, out[0][1]) and np.array_equal(gg, out[0][2])
+
+
+def test_adjoint_f32_against_f64_sphere_pack():
+    """64^3 sphere pack, T = 300: FP32 gradients against the FP64 library
+    adjoint (itself pinned to the oracle above), same relative bound."""
+    import torch
+    from paper_1611_02445_amd.autograd import CheckpointedAdjoint
+    tau, T, K = 0.8, 300, 20
+    s, _ = I.sphere_pack((64, 64, 64), 0.5, 3.0, 8.0, seed=61)
+    sp = padded(s, 7)
+    g = torch.from_numpy(_force_field(sp, 11, mean=1e-6, std=1e-7)).cuda()
+    res = {}
+    for st in ("f64", "f32"):
+        lat = new_lattice(s, tau, 7, storage=st)
+        lat.set_force(g)
+        lat.init()
+        run = CheckpointedAdjoint(lat, T, K)
+        L = run.forward(None)
+        gs, gg = run.backward()
+        res[st] = (L, gs.cpu().numpy(), gg.cpu().numpy())
+    fl = sp == 0
+    tol = T * 19 * F32_EPS * 8
+    es = np.max(np.abs(res["f32"][1][:, fl] - res["f64"][1][:, fl])) / np.abs(res["f64"][1][:, fl]).max()
+    eg = np.max(np.abs(res["f32"][2][:, fl] - res["f64"][2][:, fl])) / np.abs(res["f64"][2][:, fl]).max()
+    eL = abs(res["f32"][0] - res["f64"][0]) / abs(res["f64"][0])
+    log(f"   64^3 T={T}: L rel {eL:.2e}  dL/ds0 err {es:.2e}  dL/dg err {eg:.2e}  tol {tol:.2e}")
+    assert es <= tol and eg <= tol
+    assert eL <= 1e-3

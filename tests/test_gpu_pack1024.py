@@ -1,0 +1,79 @@
+"""The 1024x512x512 periodic sphere pack (porosity 0.2, radius U[6,16),
+seed 5) in FP32 storage at its full size: 8000 + 2000 forward steps and the
+adjoint of the last 2000 with checkpoints sized to the free HBM.  At this
+size the oracle cannot hold the box, so the adjoint is checked through
+properties that hold at any size (directional derivatives against central
+differences of the GPU forward), and the FP32 permeability against FP64 on
+the 256^3 crop at the origin (treated as periodic)."""
+import numpy as np
+import pytest
+
+from paper_1611_02445_amd import inputs as I
+
+from helpers import log, new_lattice
+
+pytestmark = pytest.mark.gpu
+
+TAU, G = 0.65, 1e-5
+
+
+@pytest.fixture(scope="module")
+def pack():
+    s, n = I.sphere_pack((512, 512, 1024), 0.2, 6.0, 16.0, seed=5)
+    log(f"[case] pack1024 spheres={n} porosity={1.0 - s.mean():.4f}")
+    return s
+
+
+def _loss(lat, state0, T, gx, shift=0.0):
+    import torch
+    cur = lat.current_state()
+    cur.copy_(state0)
+    if shift:
+        cur.view(torch.float32).add_(shift)  # every stored value; pads are never read
+    lat.set_force((gx, 0.0, 0.0))
+    lat.step(T)
+    _, _, sums = lat.macroscopic(fields=False)
+    return sums[7] / sums[4]
+
+
+def test_pack1024_f32_adjoint_directional_derivatives(pack):
+    import torch
+    from paper_1611_02445_amd.autograd import CheckpointedAdjoint
+    T = 2000
+    lat = new_lattice(pack, TAU, 7, storage="f32")
+    log(f"   n_tiles {lat.n_tiles} n_fluid {lat.n_fluid} state {lat.sizes.state_bytes / 1e9:.2f} GB")
+    lat.init()
+    lat.set_force((G, 0.0, 0.0))
+    lat.step(8000)
+    run = CheckpointedAdjoint.within_memory(lat, T)
+    log(f"   checkpoints K={run.K} K2={run.K2} lattices={run.lattices()}")
+    L = run.forward(None)
+    lam0, grad = run.backward(dense=False)
+    torch.cuda.synchronize()
+    assert run.recompute_steps > 0
+    d_g = float(grad[:, 0, :].sum())  # direction: +1 on g_x at every fluid node
+    d_s = float(lam0.view(torch.float32).double().sum())  # direction: +1 on every f_i(0)
+    s0 = run.ckpt[0]
+    eg, es = 1e-6, 1e-4
+    fd_g = (_loss(lat, s0, T, G + eg) - _loss(lat, s0, T, G - eg)) / (2 * eg)
+    fd_s = (_loss(lat, s0, T, G, es) - _loss(lat, s0, T, G, -es)) / (2 * es)
+    rg, rs = abs(fd_g - d_g) / abs(fd_g), abs(fd_s - d_s) / abs(fd_s)
+    log(f"   L {L:.6e}; g: fd {fd_g:.8e} adj {d_g:.8e} rel {rg:.2e}; s: fd {fd_s:.8e} adj {d_s:.8e} rel {rs:.2e}")
+    # FP32 adjoint over T steps: per-step rounding ~ Q 2^-24 adds up like a
+    # random walk, sqrt(T) Q 2^-24 ~ 5e-5; the FP32 forward differences and
+    # the O(eps^2) truncation are smaller
+    assert rg <= 1e-3 and rs <= 1e-3
+
+
+def test_pack1024_crop_permeability_f32_vs_f64(pack):
+    crop = np.ascontiguousarray(pack[:256, :256, :256])
+    k = {}
+    for st in ("f64", "f32"):
+        lat = new_lattice(crop, TAU, 7, storage=st)
+        lat.init()
+        lat.set_force((G, 0.0, 0.0))
+        lat.step(10000)
+        k[st] = lat.permeability(G)
+    rel = abs(k["f32"] - k["f64"]) / abs(k["f64"])
+    log(f"   crop 256^3: k64 {k['f64']:.8e} k32 {k['f32']:.8e} rel {rel:.2e}")
+    assert rel <= 1e-3
