@@ -188,7 +188,9 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
         for (int64_t d = 0; d < n; ++d) inv[perm[d]] = (int32_t)d;
         std::vector<unsigned char> host(lay.total, 0);
         TileRec *rec = reinterpret_cast<TileRec *>(host.data() + lay.rec_off);
-        int32_t *nb = reinterpret_cast<int32_t *>(host.data() + lay.nbr_off);
+        uint64_t *nbm = reinterpret_cast<uint64_t *>(host.data() + lay.nbm_off);
+        uint32_t *nbb32 = reinterpret_cast<uint32_t *>(host.data() + lay.nbb32_off);
+        uint64_t *nbb64 = reinterpret_cast<uint64_t *>(host.data() + lay.nbb64_off);
         int32_t *xyz = reinterpret_cast<int32_t *>(host.data() + lay.xyz_off);
         uint64_t next = 0;
         for (int64_t d = 0; d < n; ++d) {
@@ -200,12 +202,21 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
             } else {
                 rec[d].base = (uint64_t)d * Q * TILE;
             }
-            for (int k = 0; k < NBR_STRIDE; ++k) {
-                const int32_t v = k < 27 ? tiles->nbr[27 * i + k] : -1;
-                nb[NBR_STRIDE * d + k] = v < 0 ? -1 : inv[v];
-            }
             for (int a = 0; a < 3; ++a) xyz[4 * d + a] = tiles->tile_xyz[3 * i + a];
             xyz[4 * d + 3] = 0;
+        }
+        // neighbourhood rows (needs every tile's record first)
+        for (int64_t d = 0; d < n; ++d) {
+            const int64_t i = perm[d];
+            for (int k = 0; k < 27; ++k) {
+                const int s = nb_slot(k);
+                if (s < 0) continue;
+                const int32_t v = tiles->nbr[27 * i + k];
+                const TileRec r = v < 0 ? TileRec{0, 0} : rec[inv[v]];
+                nbm[NB_STRIDE * d + s] = r.mask;
+                nbb32[NB_STRIDE * d + s] = (uint32_t)r.base;
+                nbb64[NB_STRIDE * d + s] = r.base;
+            }
         }
         hipError_t e = hipMemcpyAsync(tables, host.data(), lay.total, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -220,7 +231,9 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
     c->L.tpw = c->params.tiles_per_wg;
     c->L.grid = (int)((n + c->L.tpw - 1) / c->L.tpw);
     c->L.tb.rec = reinterpret_cast<const TileRec *>(tb + lay.rec_off);
-    c->L.tb.nbr = reinterpret_cast<const int32_t *>(tb + lay.nbr_off);
+    c->L.tb.nbm = reinterpret_cast<const uint64_t *>(tb + lay.nbm_off);
+    c->L.tb.nbb32 = reinterpret_cast<const uint32_t *>(tb + lay.nbb32_off);
+    c->L.tb.nbb64 = reinterpret_cast<const uint64_t *>(tb + lay.nbb64_off);
     c->L.tb.xyz = reinterpret_cast<const int32_t *>(tb + lay.xyz_off);
     // every byte offset into a lattice (an FP64 adjoint lattice has the same
     // elements as the FP64 lattice) must fit 32 bits for the 32-bit kernels

@@ -54,29 +54,55 @@ inline uint64_t run_elems(uint64_t mask, int storage) {
 
 // ---------------------------------------------------------------------------
 // device table layout inside the caller's `tables` buffer
-//   [rec_off]      TileRec per tile: fluid mask, element offset of its data
-//   [nbr_off]      int32 [n_tiles][32]: the 27 neighbours, padded with -1
-//   [xyz_off]      int32 [n_tiles][4]:  corner x, y, z, 0
+//   [rec_off]    TileRec per tile: fluid mask, element offset of its data
+//   [nbm_off]    uint64 [n_tiles][20]: fluid masks of the 19 tiles a D3Q19
+//                step reads from (the tile itself, 6 face and 12 edge
+//                neighbours; corners are never needed), 0 for a missing one
+//   [nbb32_off]  uint32 [n_tiles][20]: element offsets of the same 19 tiles
+//   [nbb64_off]  uint64 [n_tiles][20]: the same offsets in 64 bits
+//   [xyz_off]    int32  [n_tiles][4]: corner x, y, z, 0
+// The neighbourhood is gathered once on the host, so a wave reads it with a
+// few wide scalar loads instead of chasing 19 tile numbers.
 // ---------------------------------------------------------------------------
 struct TileRec {
     uint64_t mask;
     uint64_t base;
 };
-constexpr int NBR_STRIDE = 32;
+constexpr int NB_STRIDE = 20;
+// slot of neighbour k = (dx+1) + 3(dy+1) + 9(dz+1) in a neighbourhood row,
+// -1 for the 8 corners
+constexpr int nb_slot(int k) {
+    int slot = 0;
+    for (int j = 0; j < 27; ++j) {
+        const int nz = (j % 3 != 1) + ((j / 3) % 3 != 1) + (j / 9 != 1);
+        if (nz == 3) {
+            if (j == k) return -1;
+            continue;
+        }
+        if (j == k) return slot;
+        ++slot;
+    }
+    return -1;
+}
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct TableLayout {
-    size_t rec_off, nbr_off, xyz_off, total;
+    size_t rec_off, nbm_off, nbb32_off, nbb64_off, xyz_off, total;
     explicit TableLayout(int64_t n_tiles) {
+        const size_t n = (size_t)n_tiles;
         rec_off = 0;
-        nbr_off = align_up(rec_off + (size_t)n_tiles * sizeof(TileRec), 256);
-        xyz_off = align_up(nbr_off + (size_t)n_tiles * NBR_STRIDE * 4, 256);
-        total = align_up(xyz_off + (size_t)n_tiles * 16, 256);
+        nbm_off = align_up(rec_off + n * sizeof(TileRec), 256);
+        nbb32_off = align_up(nbm_off + n * NB_STRIDE * 8, 256);
+        nbb64_off = align_up(nbb32_off + n * NB_STRIDE * 4, 256);
+        xyz_off = align_up(nbb64_off + n * NB_STRIDE * 8, 256);
+        total = align_up(xyz_off + n * 16, 256);
     }
 };
 
 struct DevTables {
     const TileRec *rec;
-    const int32_t *nbr;
+    const uint64_t *nbm;
+    const uint32_t *nbb32;
+    const uint64_t *nbb64;
     const int32_t *xyz;
 };
 

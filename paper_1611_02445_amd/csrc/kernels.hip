@@ -123,14 +123,21 @@ struct Nbhd {
 };
 
 template <typename OffT>
+__device__ __forceinline__ const OffT *nb_bases(const DevTables &tb);
+template <>
+__device__ __forceinline__ const uint32_t *nb_bases<uint32_t>(const DevTables &tb) { return tb.nbb32; }
+template <>
+__device__ __forceinline__ const uint64_t *nb_bases<uint64_t>(const DevTables &tb) { return tb.nbb64; }
+
+template <typename OffT>
 __device__ __forceinline__ void load_nbhd(Nbhd<OffT> &h, const DevTables &tb, int t) {
-    const int32_t *row = tb.nbr + (size_t)t * NBR_STRIDE;
+    const uint64_t *m = tb.nbm + (size_t)t * NB_STRIDE;
+    const OffT *b = nb_bases<OffT>(tb) + (size_t)t * NB_STRIDE;
 #pragma unroll
     for (int k = 0; k < 27; ++k) {
-        const int j = row[k];
-        const TileRec r = tb.rec[j < 0 ? 0 : j];
-        h.m[k] = j < 0 ? 0ull : r.mask;
-        h.base[k] = (OffT)r.base;
+        const int s = nb_slot(k);
+        h.m[k] = s < 0 ? 0ull : m[s];
+        h.base[k] = s < 0 ? OffT(0) : b[s];
     }
 }
 
@@ -271,7 +278,10 @@ template <bool REV, bool RUNS, typename S, typename OffT, int... Is>
 __device__ __forceinline__ void gather_all_impl(S (&v)[Q], const Nbhd<OffT> &h, const char *base,
                                                 const Self<RUNS, OffT> &me, int lane,
                                                 std::integer_sequence<int, Is...>) {
-    ((v[Is] = gather_one<Is, REV, RUNS, S, OffT>(h, base, me, lane)), ...);
+    // one direction at a time: the scheduler may not hoist the next
+    // direction's scalar address work above this one, which keeps the
+    // wave-uniform values of a few directions live instead of all 18
+    ((v[Is] = gather_one<Is, REV, RUNS, S, OffT>(h, base, me, lane), __builtin_amdgcn_sched_barrier(0)), ...);
 }
 
 template <bool REV, bool RUNS, typename S, typename OffT>
@@ -366,16 +376,34 @@ __device__ __forceinline__ void collide(T (&d)[Q], T rho_base, T omega, T kg, T 
         uz *= ir;
     }
     const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
-    const T uF = ux * Fx + uy * Fy + uz * Fz;
+    const T uF3 = T(3) * (ux * Fx + uy * Fy + uz * Fz);
+    const T om1 = T(1) - omega;
+    // omega deq_i = A_w + B_w P_i with A_w = omega w drho and B_w = omega w rho
+    // (model 0) or omega w (model 1); the source is G_w (3 c_i.F - uF3 +
+    // 9 (c_i.u)(c_i.F)) with G_w = kg w.  Per weight class:
+    const T bscale = MODEL == LBM_QUASI_COMPRESSIBLE ? rho : T(1);
+    const T od = omega * drho, ob = omega * bscale;
+    {
+        const T w = T(weight(0));
+        d[0] = om1 * d[0] + (w * od - (w * ob) * usq) - (kg * w) * uF3;
+    }
+    // Opposite directions share c.u and c.F up to sign, so they are updated
+    // together: P = q +- 3 c.u with q = 4.5 (c.u)^2 - 1.5 u.u, and the source
+    // splits into a shared part and +- 3 G c.F.
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 1; i < Q; ++i) {
+        const int j = opposite(i);
+        if (j < i) continue;
         const T w = T(weight(i));
+        const T A = w * od, B = w * ob, G = kg * w;
         const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
         const T cF = T(CX[i]) * Fx + T(CY[i]) * Fy + T(CZ[i]) * Fz;
-        const T P = T(3) * cu + T(4.5) * cu * cu - usq;
-        const T deq = (MODEL == LBM_QUASI_COMPRESSIBLE) ? w * (drho + rho * P) : w * (drho + P);
-        const T src = kg * w * (T(3) * (cF - uF) + T(9) * cu * cF);
-        d[i] = d[i] + omega * (deq - d[i]) + src;
+        const T q = T(4.5) * cu * cu - usq;
+        const T t = T(3) * cu;
+        const T sh = G * (T(9) * cu * cF - uF3) + A;
+        const T f = (T(3) * G) * cF;
+        d[i] = om1 * d[i] + ((sh + f) + B * (q + t));
+        d[j] = om1 * d[j] + ((sh - f) + B * (q - t));
     }
 }
 

@@ -61,7 +61,7 @@ def test_required_bytes():
         assert sz.force_bytes == 24 * 3 * 64 * na
         assert sz.grad_force_bytes == 24 * 3 * 64 * 8
         assert sz.dense_nodes == 8 * 12 * 16
-        assert sz.table_bytes >= 24 * (8 + 27 * 4 + 12)
+        assert sz.table_bytes >= 24 * (16 + 20 * (8 + 4 + 8) + 16)
 
 
 def test_null_arguments():
