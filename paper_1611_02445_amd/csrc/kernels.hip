@@ -252,6 +252,21 @@ __device__ __forceinline__ S load_elem(const char *base, OffT elem) {
 // node x - c_I (REV = false: pull streaming S) or x + c_I (REV = true: its
 // transpose S^T), or, when that node is solid or missing, the value of the
 // opposite direction at the node itself (halfway bounce-back).
+// element of block I at this lane's source node (x + (SX, SY, SZ)), for
+// every lane (valid where that node exists)
+template <int SX, int SY, int SZ, int I, bool RUNS, typename OffT>
+__device__ __forceinline__ OffT source_elem(const Nbhd<OffT> &h, int lane) {
+    OffT e = region_elem<Region<SX, SY, SZ, 0, 0, 0>, I, RUNS, OffT>(h, lane);
+    e = region_pick<SX, SY, SZ, 1, 0, 0, I, RUNS, OffT>(h, lane, e);
+    e = region_pick<SX, SY, SZ, 0, 1, 0, I, RUNS, OffT>(h, lane, e);
+    e = region_pick<SX, SY, SZ, 1, 1, 0, I, RUNS, OffT>(h, lane, e);
+    e = region_pick<SX, SY, SZ, 0, 0, 1, I, RUNS, OffT>(h, lane, e);
+    e = region_pick<SX, SY, SZ, 1, 0, 1, I, RUNS, OffT>(h, lane, e);
+    e = region_pick<SX, SY, SZ, 0, 1, 1, I, RUNS, OffT>(h, lane, e);
+    e = region_pick<SX, SY, SZ, 1, 1, 1, I, RUNS, OffT>(h, lane, e);
+    return e;
+}
+
 template <int I, bool REV, bool RUNS, typename S, typename OffT>
 __device__ __forceinline__ S gather_one(const Nbhd<OffT> &h, const char *base, const Self<RUNS, OffT> &me, int lane) {
     if constexpr (I == 0) {
@@ -262,16 +277,45 @@ __device__ __forceinline__ S gather_one(const Nbhd<OffT> &h, const char *base, c
         constexpr int SZ = REV ? CZ[I] : -CZ[I];
         constexpr int OP = opposite(I);
         const uint64_t ok_mask = source_fluid<SX, SY, SZ>(h);
-        OffT e = region_elem<Region<SX, SY, SZ, 0, 0, 0>, I, RUNS, OffT>(h, lane);
-        e = region_pick<SX, SY, SZ, 1, 0, 0, I, RUNS, OffT>(h, lane, e);
-        e = region_pick<SX, SY, SZ, 0, 1, 0, I, RUNS, OffT>(h, lane, e);
-        e = region_pick<SX, SY, SZ, 1, 1, 0, I, RUNS, OffT>(h, lane, e);
-        e = region_pick<SX, SY, SZ, 0, 0, 1, I, RUNS, OffT>(h, lane, e);
-        e = region_pick<SX, SY, SZ, 1, 0, 1, I, RUNS, OffT>(h, lane, e);
-        e = region_pick<SX, SY, SZ, 0, 1, 1, I, RUNS, OffT>(h, lane, e);
-        e = region_pick<SX, SY, SZ, 1, 1, 1, I, RUNS, OffT>(h, lane, e);
+        const OffT e = source_elem<SX, SY, SZ, I, RUNS, OffT>(h, lane);
         return load_elem<OffT, S>(base, lane_on(ok_mask) ? e : me.elem(OP));
     }
+}
+
+// The adjoint step needs S^T applied to one lattice (direction I from
+// x + c_I) and S applied to another (direction opp(I) from x - c_opp(I),
+// the same node): both come from one address computation, two loads.
+template <int I, bool RUNS, typename S, typename OffT>
+__device__ __forceinline__ void gather_pair(const Nbhd<OffT> &h, const char *rev_base, const char *fwd_base,
+                                            const Self<RUNS, OffT> &me, int lane, S &rev_I, S &fwd_op) {
+    constexpr int OP = opposite(I);
+    if constexpr (I == 0) {
+        rev_I = load_elem<OffT, S>(rev_base, me.elem(0));
+        fwd_op = load_elem<OffT, S>(fwd_base, me.elem(0));
+    } else {
+        const bool ok = lane_on(source_fluid<CX[I], CY[I], CZ[I]>(h));
+        const OffT e_rev = source_elem<CX[I], CY[I], CZ[I], I, RUNS, OffT>(h, lane);
+        const OffT e_fwd = source_elem<CX[I], CY[I], CZ[I], OP, RUNS, OffT>(h, lane);
+        rev_I = load_elem<OffT, S>(rev_base, ok ? e_rev : me.elem(OP));
+        fwd_op = load_elem<OffT, S>(fwd_base, ok ? e_fwd : me.elem(I));
+    }
+}
+
+template <bool RUNS, typename S, typename OffT, int... Is>
+__device__ __forceinline__ void gather_pairs_impl(S (&rev)[Q], S (&fwd)[Q], const Nbhd<OffT> &h, const char *rev_base,
+                                                  const char *fwd_base, const Self<RUNS, OffT> &me, int lane,
+                                                  std::integer_sequence<int, Is...>) {
+    ((gather_pair<Is, RUNS, S, OffT>(h, rev_base, fwd_base, me, lane, rev[Is], fwd[opposite(Is)]),
+      __builtin_amdgcn_sched_barrier(0)),
+     ...);
+}
+
+// rev = S^T applied to the lattice at rev_base, fwd = S applied to the one at
+// fwd_base
+template <bool RUNS, typename S, typename OffT>
+__device__ __forceinline__ void gather_pairs(S (&rev)[Q], S (&fwd)[Q], const Nbhd<OffT> &h, const char *rev_base,
+                                             const char *fwd_base, const Self<RUNS, OffT> &me, int lane) {
+    gather_pairs_impl<RUNS, S, OffT>(rev, fwd, h, rev_base, fwd_base, me, lane, std::make_integer_sequence<int, Q>{});
 }
 
 template <bool REV, bool RUNS, typename S, typename OffT, int... Is>
@@ -281,7 +325,11 @@ __device__ __forceinline__ void gather_all_impl(S (&v)[Q], const Nbhd<OffT> &h, 
     // one direction at a time: the scheduler may not hoist the next
     // direction's scalar address work above this one, which keeps the
     // wave-uniform values of a few directions live instead of all 18
-    ((v[Is] = gather_one<Is, REV, RUNS, S, OffT>(h, base, me, lane), __builtin_amdgcn_sched_barrier(0)), ...);
+    if constexpr (sizeof(S) < 8) {
+        ((v[Is] = gather_one<Is, REV, RUNS, S, OffT>(h, base, me, lane), __builtin_amdgcn_sched_barrier(0)), ...);
+    } else {
+        ((v[Is] = gather_one<Is, REV, RUNS, S, OffT>(h, base, me, lane)), ...);
+    }
 }
 
 template <bool REV, bool RUNS, typename S, typename OffT>
@@ -759,24 +807,31 @@ __device__ __forceinline__ void collide_jt(const T (&d)[Q], T rho_base, const T 
     const T ux = (jx + T(0.5) * Fx) * ir, uy = (jy + T(0.5) * Fy) * ir, uz = (jz + T(0.5) * Fz) * ir;
     const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
     const T ro = rho * omega;
-    T A = 0, q = 0, px = 0, py = 0, pz = 0, rx = 0, ry = 0, rz = 0;
+    // rest direction
+    T q = lam[0] * T(weight(0));
+    T A = q * (T(1) - usq);
+    T px = 0, py = 0, pz = 0, rx = 0, ry = 0, rz = 0;
+    // Opposite directions i, j have c_j = -c_i and equal weights, so with
+    // S = (lam_i + lam_j) w and D = (lam_i - lam_j) w their terms combine:
+    //   A += S (1 + 4.5 (c.u)^2 - 1.5 u.u) + 3 (c.u) D,   q += S,
+    //   p += c (3 rho/tau D + (9 rho/tau c.u + 9 kg c.F) S),
+    //   r += c (3 D + 9 (c.u) S)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 1; i < Q; ++i) {
+        const int j = opposite(i);
+        if (j < i) continue;
         const T w = T(weight(i));
         const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
         const T cF = T(CX[i]) * Fx + T(CY[i]) * Fy + T(CZ[i]) * Fz;
-        const T lw = lam[i] * w;
-        A += lw * (T(1) + T(3) * cu + T(4.5) * cu * cu - usq);
-        q += lw;
-        const T a3 = T(3) + T(9) * cu;
-        const T pi = lw * (ro * a3 + T(9) * kg * cF);
-        const T ri = lw * a3;
-        px += T(CX[i]) * pi;
-        py += T(CY[i]) * pi;
-        pz += T(CZ[i]) * pi;
-        rx += T(CX[i]) * ri;
-        ry += T(CY[i]) * ri;
-        rz += T(CZ[i]) * ri;
+        const T S = (lam[i] + lam[j]) * w;
+        const T D = (lam[i] - lam[j]) * w;
+        A += S * (T(1) + T(4.5) * cu * cu - usq) + T(3) * cu * D;
+        q += S;
+        const T pi = T(3) * ro * D + (T(9) * ro * cu + T(9) * kg * cF) * S;
+        const T ri = T(3) * D + T(9) * cu * S;
+        if (CX[i]) { px += T(CX[i]) * pi; rx += T(CX[i]) * ri; }
+        if (CY[i]) { py += T(CY[i]) * pi; ry += T(CY[i]) * ri; }
+        if (CZ[i]) { pz += T(CZ[i]) * pi; rz += T(CZ[i]) * ri; }
     }
     A *= omega;
     const T Vx = px - q * (T(3) * ro * ux + T(3) * kg * Fx);
@@ -868,8 +923,7 @@ __global__ __launch_bounds__(512) void k_adj_step(AdjArgs a) {
         Nbhd<OffT> h;
         load_nbhd(h, a.tb, t);
         T lam[Q], g[Q];
-        gather_all<true, true, T, OffT>(lam, h, a.eta_in, me, lane);
-        gather_all<false, true, T, OffT>(g, h, a.s, me, lane);
+        gather_pairs<true, T, OffT>(lam, g, h, a.eta_in, a.s, me, lane);
         T Fx, Fy, Fz;
         load_force<T>(a.P, t, lane, Fx, Fy, Fz);
         T gx, gy, gz;
