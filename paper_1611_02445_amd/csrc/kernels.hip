@@ -325,11 +325,7 @@ __device__ __forceinline__ void gather_all_impl(S (&v)[Q], const Nbhd<OffT> &h, 
     // one direction at a time: the scheduler may not hoist the next
     // direction's scalar address work above this one, which keeps the
     // wave-uniform values of a few directions live instead of all 18
-    if constexpr (sizeof(S) < 8) {
-        ((v[Is] = gather_one<Is, REV, RUNS, S, OffT>(h, base, me, lane), __builtin_amdgcn_sched_barrier(0)), ...);
-    } else {
-        ((v[Is] = gather_one<Is, REV, RUNS, S, OffT>(h, base, me, lane)), ...);
-    }
+    ((v[Is] = gather_one<Is, REV, RUNS, S, OffT>(h, base, me, lane), __builtin_amdgcn_sched_barrier(0)), ...);
 }
 
 template <bool REV, bool RUNS, typename S, typename OffT>
