@@ -61,21 +61,25 @@ template <> struct Codec<LBM_F16S> {
     static constexpr bool RUNS = false;
     static __device__ __forceinline__ T dec(S v, float inv_scale) { return (float)v * inv_scale; }
     static __device__ __forceinline__ S enc(T v, float scale) { return (_Float16)(v * scale); }
-    // Stochastic rounding to FP16: add 13 random bits below the FP16 mantissa
-    // to the FP32 magnitude, then drop them (the conversion is then exact for
-    // normal FP16 values).  Rounds up with probability equal to the dropped
-    // fraction, so the rounding error has zero mean: a per-step increment
-    // smaller than half an ulp is kept on average instead of being lost.
-    static __device__ __forceinline__ S enc_sr(T v, float scale, uint32_t r) {
-        const uint32_t b = (__float_as_uint(v * scale) + (r & 0x1FFFu)) & ~0x1FFFu;
-        return (_Float16)__uint_as_float(b);
+    // Stochastic rounding to FP16 with gfx950's conversion instruction: it
+    // rounds away from zero with probability equal to the discarded fraction
+    // of an FP16 ulp (normal and subnormal results alike), drawing on the high
+    // bits of r; values exact in FP16 are unchanged.  The rounding error has
+    // zero mean, so a per-step increment smaller than half an ulp is kept on
+    // average instead of being lost.
+    // The instruction writes one half of a 32-bit register and keeps the
+    // other; `pair` carries that register from one call to the next.
+    typedef _Float16 Pair __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ S enc_sr(T v, float scale, uint32_t r, Pair &pair) {
+        pair = __builtin_amdgcn_cvt_sr_f16_f32(pair, v * scale, r, false);
+        return pair[0];
     }
 };
 
 // Counter-based random bits for the FP16 stochastic rounding: an integer hash
 // (the "lowbias32" mixer of C. Wellons) of the node's coordinates and the
-// launch counter, then a Weyl sequence over the 19 directions, whose top 13
-// bits are used.
+// launch counter, then a Weyl sequence over the 19 directions, whose high bits
+// the conversion uses.
 __device__ __forceinline__ uint32_t hash32(uint32_t x) {
     x ^= x >> 16;
     x *= 0x7feb352du;
@@ -347,7 +351,7 @@ __device__ __forceinline__ void store_stream(S *p, S v) {
     __builtin_nontemporal_store(v, p);
 }
 
-template <typename S, bool RUNS, typename OffT, bool STREAM, class Value>
+template <typename S, bool RUNS, typename OffT, bool STREAM, bool ZERO_SOLID = false, class Value>
 __device__ __forceinline__ void store_tile(char *lattice, const Self<RUNS, OffT> &me, uint64_t own, bool fl, int lane,
                                            Value value) {
     S *out = reinterpret_cast<S *>(lattice);
@@ -379,11 +383,14 @@ __device__ __forceinline__ void store_tile(char *lattice, const Self<RUNS, OffT>
             for (int g = 0; g < 64 / L; ++g)
                 if ((own >> (g * L)) & G) cover |= G << (g * L);
         }
+        // value(i) is evaluated on every covered lane (callers keep the
+        // values of solid lanes defined, and zero when they pass ZERO_SOLID)
         if (lane_on(cover)) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                S *p = out + me.elem(i);
-                const S v = fl ? value(i) : S(0);
+                S *p = out + (me.base + (OffT)(i * TILE)) + lane;
+                S v = value(i);
+                if constexpr (!ZERO_SOLID) v = fl ? v : S(0);
                 if constexpr (STREAM) store_stream(p, v);
                 else *p = v;
             }
@@ -493,6 +500,12 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
     const bool fl = lane_on(own);
     const Self<RN, OffT> me(rec, lane);
     T d[Q];
+    if constexpr (!RN) {
+        // solid lanes of the plain layout store zeros: encode 0 (exact in
+        // every rounding) rather than branch around the encoding
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = T(0);
+    }
     if (fl) {  // solid nodes neither gather nor collide
         Nbhd<OffT> h;
         load_nbhd(h, a.tb, t);
@@ -511,13 +524,14 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
             const uint32_t tile_seed =
                 hash32((uint32_t)c[0] + hash32((uint32_t)c[1] + hash32((uint32_t)c[2] + hash32(a.P.launch_counter))));
             const uint32_t seed = hash32(tile_seed + (uint32_t)lane);
-            store_tile<S, RN, OffT, true>(a.dst, me, own, fl, lane, [&](int i) {
-                return C::enc_sr(d[i], a.P.scale, (seed + (uint32_t)i * 0x9E3779B9u) >> 19);
+            typename C::Pair pair = {};
+            store_tile<S, RN, OffT, true, !RN>(a.dst, me, own, fl, lane, [&](int i) {
+                return C::enc_sr(d[i], a.P.scale, seed + (uint32_t)i * 0x9E3779B9u, pair);
             });
             return;
         }
     }
-    store_tile<S, RN, OffT, true>(a.dst, me, own, fl, lane, [&](int i) { return C::enc(d[i], a.P.scale); });
+    store_tile<S, RN, OffT, true, !RN>(a.dst, me, own, fl, lane, [&](int i) { return C::enc(d[i], a.P.scale); });
 }
 
 // the paper's measurement kernels (Section 4.1): kind 1 "read/write only",
