@@ -107,6 +107,10 @@ typedef struct lbm_params {
                                0 = library default, 1 = discovery order, 2 / 3 = slabs of 4 / 8
                                tile planes with z innermost, 4 = Morton.  Only the device layout
                                changes; every dense input and output is the same for all orders. */
+    int32_t wide_offsets;   /* 0 = 32-bit lattice offsets whenever every byte offset of a lattice
+                               fits 32 bits (else 64-bit), 1 = always 64-bit.  Results are
+                               identical; 1 exists to exercise the large-lattice kernels on
+                               small inputs. */
 } lbm_params;
 
 typedef struct lbm_sizes {

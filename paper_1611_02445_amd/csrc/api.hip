@@ -57,6 +57,8 @@ int check_params(const lbm_params *p) {
         return fail(LBM_E_INVAL, "tiles_per_wg must be 0, 1, 2, 4 or 8 (got %d)", tpw);
     if (p->tile_order < 0 || p->tile_order > 4)
         return fail(LBM_E_INVAL, "tile_order must be in 0..4 (got %d)", p->tile_order);
+    if (p->wide_offsets != 0 && p->wide_offsets != 1)
+        return fail(LBM_E_INVAL, "wide_offsets must be 0 or 1 (got %d)", p->wide_offsets);
     if (p->f16_rounding != 0 && p->f16_rounding != 1)
         return fail(LBM_E_INVAL, "f16_rounding must be 0 (stochastic) or 1 (nearest) (got %d)", p->f16_rounding);
     return LBM_OK;
@@ -235,9 +237,9 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
     c->L.tb.nbb32 = reinterpret_cast<const uint32_t *>(tb + lay.nbb32_off);
     c->L.tb.nbb64 = reinterpret_cast<const uint64_t *>(tb + lay.nbb64_off);
     c->L.tb.xyz = reinterpret_cast<const int32_t *>(tb + lay.xyz_off);
-    // every byte offset into a lattice (an FP64 adjoint lattice has the same
-    // elements as the FP64 lattice) must fit 32 bits for the 32-bit kernels
-    c->L.off32 = c->state_bytes <= (size_t)UINT32_MAX;
+    // every byte offset into a lattice (an adjoint lattice has the layout and
+    // size of the state) must fit 32 bits for the 32-bit kernels
+    c->L.off32 = c->state_bytes <= (size_t)UINT32_MAX && !c->params.wide_offsets;
 
     Phys &P = c->P;
     P = Phys{};

@@ -81,3 +81,31 @@ def test_pack1024_crop_permeability_f32_vs_f64(pack):
     rel = abs(k["f32"] - k["f64"]) / abs(k["f64"])
     log(f"   crop 256^3: k64 {k['f64']:.8e} k32 {k['f32']:.8e} rel {rel:.2e}")
     assert rel <= 1e-3
+
+
+def test_pack1024_f64_large_lattice_against_f32(pack):
+    """FP64 storage of this pack needs 8.2 GB per lattice, so it runs the
+    64-bit-offset kernels at their real size (the same kernels are pinned
+    bitwise to the 32-bit ones on small inputs).  Checked here: exact mass
+    conservation and the momentum of the FP32 run (32-bit offsets, pinned to
+    the oracle) after n steps, within the FP32 bound n * 2^-24 * 8."""
+    n = 300
+    sums = {}
+    for st in ("f64", "f32"):
+        lat = new_lattice(pack, TAU, 7, storage=st)
+        if st == "f64":
+            assert lat.sizes.state_bytes > 2 ** 32
+        lat.init()
+        lat.set_force((G, 0.0, 0.0))
+        _, _, s0 = lat.macroscopic(fields=False)
+        lat.step(n)
+        _, _, s1 = lat.macroscopic(fields=False)
+        sums[st] = (s0, s1)
+        del lat
+    s0, s1 = sums["f64"]
+    drift = abs(s1[0] - s0[0]) / s0[0]
+    rel = abs(sums["f32"][1][1] - s1[1]) / abs(s1[1])
+    log(f"   f64 (64-bit offsets): mass drift {drift:.2e}; momentum x {s1[1]:.8e} vs f32 {sums['f32'][1][1]:.8e} "
+        f"rel {rel:.2e}")
+    assert drift <= 1e-13 and s1[6] == 0
+    assert rel <= n * 2.0 ** -24 * 8

@@ -188,3 +188,38 @@ def test_tile_order_bitwise_identical(order, storage):
     # counts and max are order-free; FP64 sums are reduced in device tile order
     assert np.array_equal(res[0][1][[4, 5, 6]], res[1][1][[4, 5, 6]])
     assert abs(res[0][1][0] - res[1][1][0]) <= 1e-14 * res[0][1][0]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
+def test_wide_offsets_bitwise_identical(storage):
+    """The 64-bit-offset kernels (used when a lattice exceeds 4 GiB) give the
+    same bits as the 32-bit ones: forced on a small sphere pack."""
+    import torch
+    s, _ = I.sphere_pack((24, 20, 16), 0.5, 2.0, 4.0, seed=71)
+    log(f"[case] wide offsets {storage}")
+    out = []
+    for wide in (False, True):
+        lat = new_lattice(s, 0.7, 7, storage=storage, wide_offsets=wide)
+        lat.init()
+        lat.set_force((1e-5, 2e-6, 0.0))
+        lat.step(40)
+        out.append(lat.get_state().cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_wide_offsets_adjoint_bitwise_identical(storage):
+    import torch
+    from paper_1611_02445_amd.autograd import CheckpointedAdjoint
+    s, _ = I.sphere_pack((16, 20, 24), 0.5, 2.0, 4.0, seed=72)
+    res = []
+    for wide in (False, True):
+        lat = new_lattice(s, 0.8, 7, storage=storage, wide_offsets=wide)
+        lat.init()
+        lat.set_force((1e-5, 0.0, 0.0))
+        run = CheckpointedAdjoint(lat, 9, 4)
+        L = run.forward(None)
+        gs, gg = run.backward()
+        res.append((L, gs.cpu().numpy(), gg.cpu().numpy()))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1]) and np.array_equal(res[0][2], res[1][2])
