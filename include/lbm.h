@@ -20,7 +20,8 @@
  *     18 SB (e_3 = W as in the paper's Fig. 1);
  *   - inside a tile, node (x,y,z) in 0..3 has lane/bit n = x + 4y + 16z
  *     (the XYZ map, Eq. 11);
- *   - tile-order buffers are [n_tiles][components][64];
+ *   - tile-order buffers are [n_tiles][components][64], tiles in the
+ *     context's device order (see tile_order); lbm_tiles_to_dense converts;
  *   - device pointers are plain HIP device addresses owned by the caller; the
  *     library never allocates device memory;
  *   - every call returns an lbm_status; on failure lbm_last_error() gives a
@@ -100,9 +101,10 @@ typedef struct lbm_params {
     int32_t f16_log2_scale; /* LBM_F16S: stored h = fp16(2^k (f_i - w_i rho0)), k in [0, 30] */
     int32_t tiles_per_wg;   /* tiles (wave64s) per workgroup: 1, 2, 4 or 8; 0 = default */
     int32_t f16_rounding;   /* LBM_F16S stores: 0 = stochastic (unbiased; default), 1 = nearest-even.
-                               Stochastic rounding draws its bits from a counter-based hash of
-                               (tile, node, direction, launch counter): results are reproducible
-                               for the same sequence of launches on the context. */
+                               Stochastic rounding uses gfx950's stochastic-rounding conversion
+                               with bits from a counter-based hash of (tile corner, node,
+                               direction, launch counter): results are reproducible for the same
+                               sequence of launches and do not depend on tile_order. */
     int32_t tile_order;     /* order in which the device stores and processes the kept tiles:
                                0 = library default, 1 = discovery order, 2 / 3 = slabs of 4 / 8
                                tile planes with z innermost, 4 = Morton.  Only the device layout
@@ -136,10 +138,11 @@ int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *params, lbm_siz
  *   scratch           device buffer of scratch_bytes
  *   hip_stream        hipStream_t the context launches on (NULL = default stream)
  * The tables are copied to the device and the stream is synchronised before
- * returning, so `tiles` may be freed afterwards.  Parameters are validated:
- * tau > 1/2, known storage and model, f16 scale in [0,30], tiles_per_wg in
- * {0,1,2,4,8}, f16_rounding in {0,1}; the tables are checked (every neighbour index in [-1, n_tiles),
- * no empty kept tile). */
+ * returning, so `tiles` may be freed afterwards.  Parameters are validated
+ * (LBM_E_INVAL): tau > 1/2, rho0 > 0, known storage and model, f16 scale in
+ * [0,30], tiles_per_wg in {0,1,2,4,8}, f16_rounding in {0,1}, tile_order in
+ * 0..4, wide_offsets in {0,1}; the tables are checked (every neighbour index
+ * in [-1, n_tiles), each tile its own centre neighbour, no empty kept tile). */
 int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void *state_a, void *state_b,
                void *tables, void *scratch, void *hip_stream, lbm_ctx **out);
 int lbm_destroy(lbm_ctx *ctx);
@@ -201,9 +204,11 @@ int lbm_set_state(lbm_ctx *ctx, const double *f_dense_dev, void *state);
 int lbm_tiles_to_dense(lbm_ctx *ctx, const void *tile_buf, int32_t ncomp, int32_t dtype, double *dense_dev);
 
 /* ------------------------------------------------------------------------
- * Discrete adjoint (quasi-compressible model; FP64 storage with FP64
- * arithmetic, or FP32 storage with FP32 arithmetic; FP16 storage returns
- * LBM_E_UNSUPPORTED).
+ * Discrete adjoint of the fused step (an addition: the paper has no adjoint;
+ * the forward operator is the one of Alg. 2 with Eq. 2, 3, 5, 7 and Guo
+ * forcing).  Quasi-compressible model; FP64 storage with FP64 arithmetic, or
+ * FP32 storage with FP32 arithmetic.  FP16 storage or the incompressible
+ * model return LBM_E_UNSUPPORTED; NULL buffers return LBM_E_INVAL.
  *
  * Forward: s_t = C(S s_{t-1}, F), S = pull streaming with bounce-back,
  * C = local LBGK + Guo collision.  Loss L = (1/N_fluid) sum_fluid u_x(s_T).
@@ -221,8 +226,16 @@ int lbm_tiles_to_dense(lbm_ctx *ctx, const void *tile_buf, int32_t ncomp, int32_
  * are the context's own lattices or buffers of state_bytes.  All calls are
  * asynchronous on the context's stream.
  * ------------------------------------------------------------------------ */
+/* Seed: from the forward state s_{T-1}, write eta_T and OVERWRITE
+ * grad_g_tile (grad_force_bytes, FP64, device) with the step-T contribution
+ * plus the direct dL/dg. */
 int lbm_adjoint_seed(lbm_ctx *ctx, const void *s_Tm1, void *eta_T, double *grad_g_tile);
+/* One reverse step: from eta_t and the forward state s_{t-2}, write eta_{t-1}
+ * (eta_t != eta_tm1, else LBM_E_INVAL) and ADD the step's contribution to
+ * grad_g_tile. */
 int lbm_adjoint_step(lbm_ctx *ctx, const void *s_tm2, const void *eta_t, void *eta_tm1, double *grad_g_tile);
+/* Final reverse gather: lambda_0 = S^T eta_1 = dL/ds_0 into another adjoint
+ * lattice (eta_1 != lambda_0). */
 int lbm_adjoint_final(lbm_ctx *ctx, const void *eta_1, void *lambda_0);
 /* Dense FP64 copy [19][nz][ny][nx] (device) of an adjoint lattice, and the
  * reverse; 0 at solid and dropped nodes / solid slots set to 0. */
