@@ -112,3 +112,24 @@ def test_single_fluid_node_and_all_solid():
     assert r["tile_xyz"].tolist() == [[4, 4, 4]]
     assert int(r["fluid_mask"][0]) == 1 << (3 + 4 * 2 + 16 * 1)
     assert r["nbr"][0, 13] == 0 and (r["nbr"][0] == -1).sum() == 26
+
+
+def test_table6_sphere_arrays_tile_utilisation():
+    """Tile utilisation of random sphere arrays (diameter 40, 192^3) against the
+    printed row, for the porosities where the placement rule does not matter
+    much (0.9 down to 0.3; the rule is unstated)."""
+    import json
+    import os
+    from paper_1611_02445_amd import inputs as I
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table6_spheres_tile_utilisation.json")) as fh:
+        g = json.load(fh)
+    r = g["sphere_diameter"] / 2.0
+    for p, eta_paper in zip(g["porosity"], g["tile_utilisation"]):
+        solid, _ = I.sphere_pack(tuple(g["box"]), p, r, r, seed=11, periodic=True)
+        t = T.build_tiles(solid, 7)
+        eta = t["n_fluid"] / (64.0 * t["n_tiles"])
+        assert abs((solid == 0).mean() - p) <= 0.01
+        if p >= 0.3:
+            assert abs(eta - eta_paper) <= 0.02, (p, eta, eta_paper)
+        else:
+            assert eta_paper <= eta <= eta_paper + 0.05, (p, eta, eta_paper)
