@@ -95,13 +95,19 @@ def time_storage(solid, storage, args, torch, want_state=False):
     return out
 
 
-def time_calib(solid, args, torch):
-    """The paper's measurement kernels on the same tiles and launch shape."""
+def time_calib(solid, args, torch, kernel=None, launches=None, lat=None):
+    """The paper's measurement kernels (Section 4.1) on the same tiles and
+    launch shape as the FP64 step: "read/write only" (rw) and "propagation
+    only" (prop)."""
     from paper_1611_02445_amd.lattice import Lattice
-    kind = 1 if args.kernel == "rw" else 2
-    lat = Lattice(solid, args.tau, periodic=7, storage="f64", tiles_per_wg=args.tpw, tile_order=args.order)
-    lat.init()
-    a, b = lat.state_a, lat.state_b
+    kernel = kernel or args.kernel
+    launches = launches or args.steps
+    kind = 1 if kernel == "rw" else 2
+    if lat is None:
+        lat = Lattice(solid, args.tau, periodic=7, storage="f64", tiles_per_wg=args.tpw, tile_order=args.order)
+        lat.init()
+    a, b = lat.new_state(), lat.new_state()
+    a.copy_(lat.current_state())
     for _ in range(args.warmup):
         lat.calib_step(kind, a, b)
         a, b = b, a
@@ -109,16 +115,16 @@ def time_calib(solid, args, torch):
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(lat.stream)
-    for _ in range(args.steps):
+    for _ in range(launches):
         lat.calib_step(kind, a, b)
         a, b = b, a
     ev1.record(lat.stream)
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    ms = ev0.elapsed_time(ev1) / launches
     nf = lat.n_fluid
     gbs = BYTES_PER_UPDATE["f64"] * nf / (ms / 1e3) / 1e9
-    log(f"[bench] {args.kernel}-only: {nf / (ms / 1e3) / 1e6:.1f} MFLUPS, {ms * 1e3:.1f} us, {gbs:.0f} GB/s")
-    return {"kernel": args.kernel, "ms_per_launch": ms, "MFLUPS": nf / (ms / 1e3) / 1e6, "GBs": gbs,
+    log(f"[bench] {kernel}-only: {nf / (ms / 1e3) / 1e6:.1f} MFLUPS, {ms * 1e3:.1f} us, {gbs:.0f} GB/s")
+    return {"kernel": kernel, "ms_per_launch": ms, "MFLUPS": nf / (ms / 1e3) / 1e6, "GBs": gbs,
             "frac": gbs / HBM_PEAK_GBS, "fluid_nodes": nf, "tiles": lat.n_tiles}
 
 
@@ -251,6 +257,37 @@ def time_pack1024(args, torch):
     return out
 
 
+def sweep_sphere_arrays(args, torch):
+    """Random sphere arrays of diameter 40 in a 192^3 periodic box at the nine
+    porosities of the paper's sparse-geometry table (Section 4.6, Table 6):
+    tile utilisation and MFLUPS of the step (FP64 and FP32, both models)."""
+    from paper_1611_02445_amd import inputs
+    from paper_1611_02445_amd.lattice import Lattice
+    rows = []
+    for p in (0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2, 0.1):
+        solid, _ = inputs.sphere_pack((192, 192, 192), p, 20.0, 20.0, seed=11)
+        row = {"porosity": p}
+        for st in ("f64", "f32"):
+            for model in ("inc", "qc"):
+                lat = Lattice(solid, 0.7, periodic=7, storage=st, model=model)
+                lat.init()
+                lat.set_force((1e-6, 0.0, 0.0))
+                lat.step(args.warmup)
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record(lat.stream)
+                lat.step(500)
+                ev1.record(lat.stream)
+                torch.cuda.synchronize()
+                row["eta_t"] = round(lat.tiling.eta_t, 4)
+                row["fluid_nodes"] = lat.n_fluid
+                row[f"MFLUPS_{st}_{model}"] = round(lat.n_fluid * 500 / (ev0.elapsed_time(ev1) / 1e3) / 1e6, 1)
+                del lat
+        log(f"[bench] spheres192 porosity {p}: eta_t {row['eta_t']} f64 qc {row['MFLUPS_f64_qc']} "
+            f"f32 qc {row['MFLUPS_f32_qc']} MFLUPS")
+        rows.append(row)
+    return rows
+
+
 def cpu_baseline(solid, args):
     """The oracle as it stands, on the same geometry, for a bounded number of
     steps (about --cpu-seconds of CPU work)."""
@@ -294,6 +331,8 @@ def main():
     ap.add_argument("--adj-k", type=int, default=100, help="adjoint checkpoint interval K")
     ap.add_argument("--pack1024", action="store_true",
                     help="also run the 1024x512x512 FP32 forward + adjoint workload (about 2 minutes)")
+    ap.add_argument("--sweep192", action="store_true",
+                    help="also time the step on 192^3 random sphere arrays at porosities 0.9..0.1")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -352,6 +391,7 @@ def main():
             "tiles": lat.n_tiles,
             "fluid_nodes": nf,
             "eta_t": round(lat.tiling.eta_t, 6),
+            "porosity": round(float((solid == 0).mean()), 6),
             "storage": "f64",
             "workgroups": lat.info()["grid_blocks"],
             "tiles_per_workgroup": -(-lat.n_tiles // lat.info()["grid_blocks"]),
@@ -375,6 +415,14 @@ def main():
     }
     if traffic is not None:
         result["roofline"]["traffic_bytes_per_fluid_update"] = round(traffic / nf, 1)
+    # the paper's measurement kernels on the same tiles: the practical ceiling
+    # of this layout (read/write only) and the cost of the gather alone
+    result["paper_kernels"] = {}
+    for kname in ("rw", "prop"):
+        c = time_calib(solid, args, torch, kernel=kname, launches=min(args.steps, 500), lat=lat)
+        result["paper_kernels"]["read_write_only" if kname == "rw" else "propagation_only"] = {
+            "MFLUPS": round(c["MFLUPS"], 1), "ms_per_launch": round(c["ms_per_launch"], 6),
+            "hbm_frac_algorithmic": round(c["frac"], 4)}
 
     variants = {}
     for st in [v for v in args.variants.split(",") if v]:
@@ -403,6 +451,9 @@ def main():
         torch.cuda.empty_cache()
     if args.pack1024:
         result["pack1024"] = time_pack1024(args, torch)
+        torch.cuda.empty_cache()
+    if args.sweep192:
+        result["sphere_arrays_192"] = sweep_sphere_arrays(args, torch)
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
