@@ -346,13 +346,22 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     if args.copy_calib:
+        # a plain device copy of known size: the counter calibration, and the
+        # practical read+write bandwidth of the part
         n = args.copy_calib * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
         for _ in range(5):
             b.copy_(a)
+        ev1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calib_bytes": n * 8, "launches": 5}), flush=True)
+        ms = ev0.elapsed_time(ev1) / 5
+        print(json.dumps({"copy_calib_bytes": n * 8, "launches": 6, "ms_per_copy": ms,
+                          "read_plus_write_GBs": 2 * n * 8 / (ms / 1e3) / 1e9}), flush=True)
         return
     solid = build_case(args)
     if args.kernel != "step":
@@ -395,6 +404,7 @@ def main():
             "storage": "f64",
             "workgroups": lat.info()["grid_blocks"],
             "tiles_per_workgroup": -(-lat.n_tiles // lat.info()["grid_blocks"]),
+            "tile_order": {0: "morton", 1: "discovery", 2: "slabs4", 3: "slabs8", 4: "morton"}[args.order],
         },
         "roofline": {
             "bound": "hbm",
@@ -415,6 +425,24 @@ def main():
     }
     if traffic is not None:
         result["roofline"]["traffic_bytes_per_fluid_update"] = round(traffic / nf, 1)
+    # a plain device copy of one lattice's size: what the part sustains for
+    # equal read and write traffic, as context for the 8 TB/s peak
+    nb = lat.sizes.state_bytes // 8
+    ca = torch.ones(nb, dtype=torch.float64, device="cuda")
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(20):
+        cb.copy_(ca)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * nb * 8 / (ev0.elapsed_time(ev1) / 20 / 1e3) / 1e9
+    del ca, cb
+    result["copy_ceiling"] = {"read_plus_write_GBs": round(copy_gbs, 1), "bytes_each_way": nb * 8,
+                              "step_algorithmic_frac_of_copy": round(achieved / copy_gbs, 4)}
+    log(f"[bench] device copy {copy_gbs:.0f} GB/s read+write; step at {achieved / copy_gbs:.3f} of it")
     # the paper's measurement kernels on the same tiles: the practical ceiling
     # of this layout (read/write only) and the cost of the gather alone
     result["paper_kernels"] = {}

@@ -106,9 +106,11 @@ typedef struct lbm_params {
                                direction, launch counter): results are reproducible for the same
                                sequence of launches and do not depend on tile_order. */
     int32_t tile_order;     /* order in which the device stores and processes the kept tiles:
-                               0 = library default, 1 = discovery order, 2 / 3 = slabs of 4 / 8
-                               tile planes with z innermost, 4 = Morton.  Only the device layout
-                               changes; every dense input and output is the same for all orders. */
+                               0 = library default (Morton), 1 = discovery order, 2 / 3 = slabs of
+                               4 / 8 tile planes with z innermost, 4 = Morton (z-order of the tile
+                               coordinates).  Only the device layout changes; every dense input
+                               and output is the same for all orders (FP64 sums may differ in the
+                               last bits: their summation order follows the tiles). */
     int32_t wide_offsets;   /* 0 = 32-bit lattice offsets whenever every byte offset of a lattice
                                fits 32 bits (else 64-bit), 1 = always 64-bit.  Results are
                                identical; 1 exists to exercise the large-lattice kernels on
