@@ -97,7 +97,8 @@ def test_autograd_function():
 def test_adjoint_full_size_finite_differences():
     """128^3 periodic sphere pack, porosity 0.5, radius U[4,12), tau 0.8,
     T = 2000, checkpoints every 100 steps, per-node g_x ~ N(1e-6, 1e-7).
-    Central differences of the GPU forward at random fluid nodes."""
+    Central differences of the GPU forward: g_x at 32 random fluid nodes,
+    f_i(0) for three directions at 4 of them."""
     import torch
     from paper_1611_02445_amd.autograd import CheckpointedAdjoint
     tau, T, K = 0.8, 2000, 100
@@ -127,6 +128,7 @@ def test_adjoint_full_size_finite_differences():
 
     fluid = np.flatnonzero(sp.ravel() == 0)
     nodes = rng.choice(fluid, 8, replace=False)
+    nodes = np.concatenate([nodes, rng.choice(np.setdiff1d(fluid, nodes), 24, replace=False)])
     worst = 0.0
     gmax = np.abs(gg[0]).max()
     for n in nodes:
