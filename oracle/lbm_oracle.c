@@ -12,10 +12,10 @@
  * What is computed (all on a dense box, node index x + nx*(y + ny*z),
  * distributions stored as f[i][node]):
  *
- *   - streaming in pull form (Section 3.1: every node gathers f_i from the node
- *     it came from; Alg. 2), with halfway bounce-back at solid or missing
- *     neighbours (Section 2.2: no propagation from or to solid nodes; walls are
- *     bounce-back),
+ *   - streaming in pull form (Sections 2.3 and 3.4: every node gathers f_i
+ *     from the node it came from; Alg. 2), with halfway bounce-back at solid or
+ *     missing neighbours (Section 3.4: no propagation from or to solid nodes;
+ *     Section 2.2: walls are bounce-back),
  *   - LBGK collision (Eq. 2 and Eq. 7) with the quasi-compressible equilibrium
  *     (Eq. 3) and velocity (Eq. 5), or the incompressible pair (Eq. 4, Eq. 6),
  *   - a body force.  The paper drives its flows by boundaries only, so the

@@ -1,19 +1,21 @@
 // gfx950 kernels of the tiled D3Q19 lattice-Boltzmann method.
 //
 // Mapping (re-designed for CDNA4 from the paper's thread mapping, Section 3.1):
-// one 4x4x4 tile = one wave64, lane n = x + 4y + 16z.  A lattice is stored per
-// tile as 19 blocks of 64 slots ("data block", Section 3.2).
+// one 4x4x4 tile = one wave64, lane n = x + 4y + 16z.  A tile's values form
+// 19 blocks, one per direction ("data block", Section 3.2).
 //
-// Slot order inside a block.  With FP64 and FP32 storage the tile's fluid
-// nodes are packed into the leading slots in node order (slot = number of
-// fluid nodes of the tile with a smaller node index), so a block of k fluid
-// nodes occupies ceil(k/L) 128-byte lines (L = 16 FP64 or 32 FP32 values)
-// instead of every line that holds one fluid node.  With FP16 storage a block
-// is exactly one 128-byte line and slot = node index.  This replaces the
-// paper's per-direction node maps (Eq. 11-13), tuned for 32-byte Kepler
-// sectors: at 128-byte lines what matters is how many lines a block touches.
+// Layout of a tile's blocks.  With FP64 and FP32 storage a tile with k fluid
+// nodes owns one run of 19 * k values, block i at offset i * k, the node at
+// slot = number of fluid nodes of the tile with a smaller node index; the run
+// is padded to whole 128-byte lines, so solid nodes take no space and only
+// lines holding fluid values are read or written.  With FP16 storage a block
+// is 64 values, exactly one 128-byte line, and slot = node index.  This
+// replaces the paper's per-direction node maps (Eq. 11-13), tuned for 32-byte
+// Kepler sectors: at 128-byte lines what matters is how many lines a block
+// touches.
 //
-// Streaming is a pull (gather) fused with collision (Section 2.4, Alg. 2).
+// Streaming is a pull (gather) fused with collision (Sections 2.3 and 3.4,
+// Alg. 2).
 // For every direction the lanes split into at most four regions by which
 // neighbour tile holds their source node; inside a region the source node is
 // this lane's index plus a constant, so its slot is

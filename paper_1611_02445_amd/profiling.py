@@ -17,18 +17,28 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+def _code_only(text):
+    """Source text without comments and blank space: a counter summary stays
+    valid when only the comments of the kernels change."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
-    """Hash of the kernel sources; a counter summary is valid only for it."""
+    """Hash of the kernel code (comments ignored); a counter summary is valid
+    only for it."""
     h = hashlib.sha256()
     for name in ("kernels.hip", "common.hpp", "kernels.hpp"):
-        with open(os.path.join(HERE, "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(HERE, "csrc", name), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
