@@ -28,7 +28,7 @@ sys.path.insert(0, HERE)
 
 METRIC = "MFLUPS + % HBM roofline, FP64 vs FP32/FP16 storage at stated error; adjoint MFLUPS"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_UPDATE = {"f64": 2 * 19 * 8, "f32": 2 * 19 * 4, "f16s": 2 * 19 * 2}
+BYTES_PER_UPDATE = {"f64": 2 * 19 * 8, "f32": 2 * 19 * 4, "f32u": 2 * 19 * 4, "f16s": 2 * 19 * 2}
 PROFILE_DIR = os.path.join(HERE, "profiles")
 
 
@@ -61,7 +61,9 @@ def build_case(args):
 
 def time_storage(solid, storage, args, torch, want_state=False):
     from paper_1611_02445_amd.lattice import Lattice
-    lat = Lattice(solid, args.tau, periodic=7, storage=storage, tiles_per_wg=args.tpw, tile_order=args.order)
+    # "f32u": FP32 storage of f itself (the paper's form), an ablation of the shift
+    lat = Lattice(solid, args.tau, periodic=7, storage="f32" if storage == "f32u" else storage,
+                  tiles_per_wg=args.tpw, tile_order=args.order, f32_unshifted=storage == "f32u")
     lat.init()
     lat.set_force((args.g, 0.0, 0.0))
     log(f"[bench] {storage}: tiles={lat.n_tiles} fluid={lat.n_fluid} eta_t={lat.tiling.eta_t:.4f}")
@@ -324,7 +326,8 @@ def main():
     ap.add_argument("--order", type=int, default=0, help="device tile order (0 = library default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="f32,f16s", help="extra storage variants ('' for none)")
+    ap.add_argument("--variants", default="f32,f16s,f32u",
+                    help="extra storage variants ('' for none); f32u = FP32 without the shift (ablation)")
     ap.add_argument("--kernel", default="step", choices=["step", "rw", "prop"],
                     help="time the fused step, or the paper's read/write-only (rw) or propagation-only (prop) kernel")
     ap.add_argument("--adj-steps", type=int, default=2000, help="adjoint horizon T (0 = skip the adjoint)")

@@ -115,6 +115,9 @@ typedef struct lbm_params {
                                fits 32 bits (else 64-bit), 1 = always 64-bit.  Results are
                                identical; 1 exists to exercise the large-lattice kernels on
                                small inputs. */
+    int32_t f32_unshifted;  /* LBM_F32 only: 1 stores f_i itself instead of f_i - w_i rho0 (the
+                               paper's FP32 storage; kept as an ablation of the shift), 0 =
+                               shifted (default).  Must be 0 for other storage types. */
 } lbm_params;
 
 typedef struct lbm_sizes {
@@ -143,7 +146,8 @@ int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *params, lbm_siz
  * returning, so `tiles` may be freed afterwards.  Parameters are validated
  * (LBM_E_INVAL): tau > 1/2, rho0 > 0, known storage and model, f16 scale in
  * [0,30], tiles_per_wg in {0,1,2,4,8}, f16_rounding in {0,1}, tile_order in
- * 0..4, wide_offsets in {0,1}; the tables are checked (every neighbour index
+ * 0..4, wide_offsets in {0,1}, f32_unshifted in {0,1} (1 only with LBM_F32);
+ * the tables are checked (every neighbour index
  * in [-1, n_tiles), each tile its own centre neighbour, no empty kept tile). */
 int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void *state_a, void *state_b,
                void *tables, void *scratch, void *hip_stream, lbm_ctx **out);

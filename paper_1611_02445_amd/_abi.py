@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("rho0", ctypes.c_double), ("storage", ctypes.c_int32),
                 ("model", ctypes.c_int32), ("f16_log2_scale", ctypes.c_int32), ("tiles_per_wg", ctypes.c_int32),
                 ("f16_rounding", ctypes.c_int32), ("tile_order", ctypes.c_int32),
-                ("wide_offsets", ctypes.c_int32)]
+                ("wide_offsets", ctypes.c_int32), ("f32_unshifted", ctypes.c_int32)]
 
 
 class Sizes(ctypes.Structure):

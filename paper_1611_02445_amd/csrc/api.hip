@@ -59,6 +59,10 @@ int check_params(const lbm_params *p) {
         return fail(LBM_E_INVAL, "tile_order must be in 0..4 (got %d)", p->tile_order);
     if (p->wide_offsets != 0 && p->wide_offsets != 1)
         return fail(LBM_E_INVAL, "wide_offsets must be 0 or 1 (got %d)", p->wide_offsets);
+    if (p->f32_unshifted != 0 && p->f32_unshifted != 1)
+        return fail(LBM_E_INVAL, "f32_unshifted must be 0 or 1 (got %d)", p->f32_unshifted);
+    if (p->f32_unshifted && p->storage != LBM_F32)
+        return fail(LBM_E_INVAL, "f32_unshifted applies to FP32 storage only");
     if (p->f16_rounding != 0 && p->f16_rounding != 1)
         return fail(LBM_E_INVAL, "f16_rounding must be 0 (stochastic) or 1 (nearest) (got %d)", p->f16_rounding);
     return LBM_OK;
@@ -248,7 +252,8 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
     P.omega = 1.0 / params->tau;
     P.kg = 1.0 - 1.0 / (2.0 * params->tau);
     P.rho0 = params->rho0;
-    P.rho_base = params->storage == LBM_F64 ? 0.0 : params->rho0;
+    // reduced storage holds f_i - w_i rho0 unless FP32 is asked to store f_i
+    P.rho_base = (params->storage == LBM_F64 || params->f32_unshifted) ? 0.0 : params->rho0;
     P.field = nullptr;
     P.scale = params->storage == LBM_F16S ? std::ldexp(1.0f, params->f16_log2_scale) : 1.0f;
     P.inv_scale = 1.0f / P.scale;

@@ -32,20 +32,25 @@ def _run(solid, tau, periodic, storage, steps, g, f0=None, **kw):
     return lat
 
 
-@pytest.mark.parametrize("storage,model", [("f32", "qc"), ("f16s", "qc"), ("f32", "inc"), ("f16s", "inc")])
+@pytest.mark.parametrize("storage,model", [("f32", "qc"), ("f16s", "qc"), ("f32", "inc"), ("f16s", "inc"),
+                                           ("f32u", "qc")])
 def test_reduced_storage_against_oracle(storage, model):
     tau, steps, g = 0.7, 100, (1e-5, 2e-6, 0.0)
     s, _ = I.sphere_pack((24, 24, 24), 0.5, 2.0, 5.0, seed=51)
     sp = padded(s, 7)
     f0 = perturbed_state(sp, 8, amp=0.01)
-    lat = _run(s, tau, 7, storage, steps, g, f0=f0, model=model)
+    kw = dict(model=model)
+    if storage == "f32u":  # FP32 of f itself: rounding relative to |f|, not |f - w rho0|
+        kw["f32_unshifted"] = True
+    lat = _run(s, tau, 7, "f32" if storage == "f32u" else storage, steps, g, f0=f0, **kw)
     got = lat.get_state().cpu().numpy()
     ref = O.run(f0, sp, tau, steps, force=np.array(g), periodic=7, model={"qc": 0, "inc": 1}[model])
     fl = sp == 0
     c, w, _ = O.lattice()
-    d = np.abs(ref - w[:, None, None, None])[:, fl].max()
+    shift = 0.0 if storage == "f32u" else 1.0
+    d = np.abs(ref - shift * w[:, None, None, None])[:, fl].max()
     err = np.abs(got[:, fl] - ref[:, fl]).max()
-    bound = steps * 2.0 ** -24 * d * 8 if storage == "f32" else steps * 2.0 ** -10 * d
+    bound = steps * 2.0 ** -24 * d * 8 if storage in ("f32", "f32u") else steps * 2.0 ** -10 * d
     log(f"[case] {storage} {model}: max |df| {err:.3e}, bound {bound:.3e}, max|d| {d:.3e}")
     assert err <= bound
 
