@@ -20,7 +20,8 @@ EXPORTS = [
     "lbm_build_tiles", "lbm_tiles_free", "lbm_required_bytes", "lbm_create", "lbm_destroy", "lbm_init",
     "lbm_set_force", "lbm_step", "lbm_step_buf", "lbm_current_state", "lbm_macroscopic", "lbm_macroscopic_buf",
     "lbm_permeability", "lbm_get_state", "lbm_set_state", "lbm_tiles_to_dense", "lbm_adjoint_seed",
-    "lbm_adjoint_step", "lbm_adjoint_final", "lbm_adjoint_get", "lbm_adjoint_set", "lbm_calib_step", "lbm_info", "lbm_last_error", "lbm_version",
+    "lbm_adjoint_step", "lbm_adjoint_final", "lbm_adjoint_get", "lbm_adjoint_set", "lbm_calib_step", "lbm_info",
+    "lbm_last_error", "lbm_version",
 ]
 
 
@@ -87,6 +88,8 @@ def lib():
         "lbm_adjoint_seed": ([P, P, P, P], ctypes.c_int),
         "lbm_adjoint_step": ([P, P, P, P, P], ctypes.c_int),
         "lbm_adjoint_final": ([P, P, P], ctypes.c_int),
+        "lbm_adjoint_get": ([P, P, P], ctypes.c_int),
+        "lbm_adjoint_set": ([P, P, P], ctypes.c_int),
         "lbm_calib_step": ([P, i32, P, P], ctypes.c_int),
         "lbm_info": ([P, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)],
                      ctypes.c_int),

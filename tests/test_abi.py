@@ -23,6 +23,13 @@ def test_header_matches_binding_list():
     assert declared_functions() == sorted(_abi.EXPORTS)
 
 
+def test_every_export_has_a_ctypes_signature():
+    L = _abi.lib()
+    for name in _abi.EXPORTS:
+        fn = getattr(L, name)
+        assert fn.argtypes is not None, name
+
+
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(_abi.LIB_PATH)
     for name in declared_functions():
