@@ -231,7 +231,7 @@ def time_pack1024(args, torch):
            "forward_MFLUPS": round(nf / (fwd_ms / 1e3) / 1e6, 1),
            "forward_hbm_frac": round(BYTES_PER_UPDATE["f32"] * nf / (fwd_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
            "checkpointed_forward_MFLUPS": round(nf * T / (ckpt_fwd_ms / 1e3) / 1e6, 1),
-           "adjoint_T": T, "K": run.K, "K2": run.K2, "lattices": run.lattices(),
+           "adjoint_T": T, "checkpoint_intervals": run.intervals, "lattices": run.lattices(),
            "memory_GB": round(run.memory_bytes() / 1e9, 1), "recompute_steps": run.recompute_steps,
            "MFLUPS_adjoint_kernels": round(nf * T / (kern_ms / 1e3) / 1e6, 1),
            "MFLUPS_backward_incl_recompute": round(nf * T / (back_ms / 1e3) / 1e6, 1),
@@ -240,7 +240,7 @@ def time_pack1024(args, torch):
     out["adjoint_hbm_frac"] = round(out["bytes_per_fluid_update_adjoint"] * nf / (kern_ms / T / 1e3) / 1e9
                                     / HBM_PEAK_GBS, 4)
     log(f"[bench] pack1024: forward {out['forward_MFLUPS']} MFLUPS, adjoint {out['MFLUPS_adjoint_kernels']} "
-        f"MFLUPS kernels, {out['MFLUPS_backward_incl_recompute']} incl. recompute (K={run.K}, K2={run.K2})")
+        f"MFLUPS kernels, {out['MFLUPS_backward_incl_recompute']} incl. recompute (intervals {run.intervals})")
     del run, lat
     torch.cuda.empty_cache()
     crop = np.ascontiguousarray(solid[:256, :256, :256])

@@ -13,16 +13,17 @@ It needs the states s_{T-1}, ..., s_0 in decreasing order.  The forward pass
 keeps every K-th state (checkpoints s_0, s_K, s_2K, ...).  With one level the
 backward pass recomputes one segment of K states at a time from its
 checkpoint into a ring of buffers and consumes it from the top: one extra
-forward step per adjoint step, ceil(T/K) + K + 1 lattices.  With a second
-level (K2 < K) each segment is first re-run once keeping every K2-th state,
-and then each sub-segment of K2 states is recomputed into the ring: about two
-extra forward steps per adjoint step, ceil(T/K) + ceil(K/K2) + K2 lattices.
-``plan_checkpoints`` picks (K, K2) with the least recomputation that fits a
-lattice budget.
+forward step per adjoint step, ceil(T/K) + K + 1 lattices.  Each further level
+(intervals K > K2 > K3 ...) first re-runs a segment once keeping every
+K2-th state and then treats each sub-segment the same way, down to a ring of
+the last interval: about one more forward step per adjoint step per level,
+for ceil(T/K) + ceil(K/K2) + ... + K_last lattices.  ``plan_checkpoints``
+picks the intervals with the least recomputation that fit a lattice budget.
 
 This module only orders library calls; every step, adjoint step, conversion
 and reduction runs in the HIP library.
 """
+import functools
 import math
 
 import torch
@@ -30,73 +31,117 @@ import torch
 from .lattice import Lattice
 
 
-def _recompute_cost(T, K, K2):
-    """Forward steps re-run by the backward pass for checkpoint intervals
-    (K, K2); K2 = None for one level."""
-    def segment(length):
-        if K2 is None:
-            return length - 1
-        n2 = math.ceil(length / K2)
-        # one pass to the last second-level checkpoint, then each sub-segment
-        return (n2 - 1) * K2 + (length - n2)
-    cost = (T // K) * segment(K)
-    if T % K:
-        cost += segment(T % K)
+def _intervals(T, K, inner):
+    """Normalised checkpoint intervals: K capped at T, then each inner interval
+    strictly below the previous one (others dropped)."""
+    out = [int(min(K, T))]
+    for k in inner:
+        if k is None:
+            continue
+        if k < 1:
+            raise ValueError("checkpoint intervals must be >= 1")
+        if k < out[-1]:
+            out.append(int(k))
+    return out
+
+
+@functools.lru_cache(maxsize=None)
+def _segment_cost(length, inner):
+    """Forward steps re-run to hand out the `length` states of a segment, given
+    the inner intervals below its level (a tuple; empty = ring)."""
+    if not inner:
+        return length - 1
+    K = inner[0]
+    n = math.ceil(length / K)
+    cost = (n - 1) * K  # one pass to the segment's last inner checkpoint
+    full = length // K
+    cost += full * _segment_cost(K, inner[1:])
+    if length % K:
+        cost += _segment_cost(length % K, inner[1:])
     return cost
 
 
-def lattices_needed(T, K, K2=None):
-    """Forward-state lattices held at once (checkpoints, second-level
-    checkpoints, ring and two step buffers), for T steps."""
-    K = min(K, T)
-    n1 = math.ceil(T / K)
-    if K2 is None or K2 >= K:
-        return n1 + (K - 1) + 2
-    return n1 + (math.ceil(K / K2) - 1) + (K2 - 1) + 2
+def _recompute_cost(T, K, *inner):
+    """Forward steps re-run by the backward pass for checkpoint intervals
+    (K, K2, ...); no inner interval (or None) = one level."""
+    iv = _intervals(T, K, inner)
+    K, rest = iv[0], tuple(iv[1:])
+    cost = (T // K) * _segment_cost(K, rest)
+    if T % K:
+        cost += _segment_cost(T % K, rest)
+    return cost
 
 
-def plan_checkpoints(T, max_lattices):
-    """(K, K2) for T adjoint steps within max_lattices forward lattices: one
-    level when it fits (the smallest K that fits, i.e. the least recompute),
-    else two levels with the least recompute.  Raises when even two levels do
-    not fit."""
-    T = int(T)
-    for K in range(1, T + 1):
-        if lattices_needed(T, K) <= max_lattices:
-            return K, None
+def lattices_needed(T, K, *inner):
+    """Forward-state lattices held at once (checkpoints of every level, the
+    ring and two step buffers), for T steps."""
+    iv = _intervals(T, K, inner)
+    n = math.ceil(T / iv[0])
+    for a, b in zip(iv[:-1], iv[1:]):
+        n += math.ceil(a / b) - 1
+    return n + (iv[-1] - 1) + 2
+
+
+def plan_checkpoints(T, max_lattices, max_levels=3):
+    """Checkpoint intervals (a tuple K, K2, ...) for T adjoint steps within
+    max_lattices forward lattices, with the fewest levels that fit and, among
+    those, the least recomputation.  Raises when max_levels do not fit."""
+    T, M = int(T), int(max_lattices)
+    for K in range(1, T + 1):  # one level: the smallest K that fits
+        if lattices_needed(T, K) <= M:
+            return (K,)
+    if max_levels < 2:
+        raise ValueError(f"{T} adjoint steps do not fit in {M} lattices with one level")
     best = None
     for K in range(2, T + 1):
-        n1 = math.ceil(T / K)
-        if n1 + 2 > max_lattices:
+        if math.ceil(T / K) + 2 > M:
             continue
-        for K2 in range(1, min(K, max_lattices)):
-            if lattices_needed(T, K, K2) > max_lattices:
+        for K2 in range(1, min(K, M)):
+            if lattices_needed(T, K, K2) <= M:
+                c = _recompute_cost(T, K, K2)
+                if best is None or c < best[0]:
+                    best = (c, (K, K2))
+    if best is not None:
+        return best[1]
+    if max_levels >= 3:
+        ks = sorted({math.ceil(T / n) for n in range(1, M + 1)})
+        for K in ks:
+            if K < 3 or math.ceil(T / K) + 2 > M:
                 continue
-            c = _recompute_cost(T, K, K2)
-            if best is None or c < best[0]:
-                best = (c, K, K2)
-    if best is None:
-        raise ValueError(f"{T} adjoint steps do not fit in {max_lattices} lattices")
-    return best[1], best[2]
+            for K2 in sorted({math.ceil(K / n) for n in range(2, M + 1)}):
+                if K2 < 2 or K2 >= K:
+                    continue
+                for K3 in range(1, min(K2, M)):
+                    if lattices_needed(T, K, K2, K3) <= M:
+                        c = _recompute_cost(T, K, K2, K3)
+                        if best is None or c < best[0]:
+                            best = (c, (K, K2, K3))
+        if best is not None:
+            return best[1]
+    raise ValueError(f"{T} adjoint steps do not fit in {M} lattices with {max_levels} levels")
 
 
 class CheckpointedAdjoint:
     """Forward run with checkpoints and the matching reverse sweep on a Lattice
-    (FP64 or FP32 storage, quasi-compressible model)."""
+    (FP64 or FP32 storage, quasi-compressible model).  Intervals: K for the
+    forward checkpoints, then optional inner intervals K2 > K3 > ..."""
 
-    def __init__(self, lat: Lattice, T: int, K: int, K2=None):
+    def __init__(self, lat: Lattice, T: int, K: int, *inner):
         if T < 1:
             raise ValueError("T must be >= 1")
-        if K < 1 or (K2 is not None and K2 < 1):
+        if K < 1:
             raise ValueError("checkpoint intervals must be >= 1")
-        self.lat, self.T, self.K = lat, int(T), int(min(K, T))
-        self.K2 = None if K2 is None or K2 >= self.K else int(K2)
+        self.lat, self.T = lat, int(T)
+        self.intervals = _intervals(self.T, K, inner)
+        self.K = self.intervals[0]
+        self.K2 = self.intervals[1] if len(self.intervals) > 1 else None
         self.n_ckpt = math.ceil(self.T / self.K)
         self.ckpt = [lat.new_state() for _ in range(self.n_ckpt)]  # s_0, s_K, ...
-        inner = self.K if self.K2 is None else self.K2
-        # ring slot 0 is always a checkpoint buffer (first or second level)
-        self.ring = [lat.new_state() for _ in range(inner - 1)]
-        self.ckpt2 = [] if self.K2 is None else [lat.new_state() for _ in range(math.ceil(self.K / self.K2) - 1)]
+        # inner level j keeps ceil(K_{j-1}/K_j) - 1 states besides its parent's
+        self.inner_ckpt = [[lat.new_state() for _ in range(math.ceil(a / b) - 1)]
+                           for a, b in zip(self.intervals[:-1], self.intervals[1:])]
+        # ring slot 0 is always a checkpoint buffer of the level above
+        self.ring = [lat.new_state() for _ in range(self.intervals[-1] - 1)]
         self.tmp = [lat.new_state(), lat.new_state()]
         self.eta = [lat.new_adjoint(), lat.new_adjoint()]
         self.grad = lat.new_grad()
@@ -111,11 +156,10 @@ class CheckpointedAdjoint:
             free_bytes, _ = torch.cuda.mem_get_info(lat.device)
         s = lat.sizes
         avail = free_bytes - reserve_bytes - 2 * s.adjoint_bytes - s.grad_force_bytes
-        K, K2 = plan_checkpoints(T, max(int(avail // max(s.state_bytes, 1)), 0))
-        return cls(lat, T, K, K2)
+        return cls(lat, T, *plan_checkpoints(T, max(int(avail // max(s.state_bytes, 1)), 0)))
 
     def lattices(self):
-        return len(self.ckpt) + len(self.ckpt2) + len(self.ring) + len(self.tmp)
+        return len(self.ckpt) + sum(len(b) for b in self.inner_ckpt) + len(self.ring) + len(self.tmp)
 
     def memory_bytes(self):
         s = self.lat.sizes
@@ -153,28 +197,32 @@ class CheckpointedAdjoint:
         self.recompute_steps += length - 1
         return bufs
 
+    def _segment_reversed(self, first, length, level):
+        """The `length` states of a segment starting with the state in buffer
+        `first`, last first; `level` indexes the inner intervals."""
+        if level + 1 >= len(self.intervals):
+            yield from reversed(self._ring(first, length))
+            return
+        K = self.intervals[level + 1]
+        n = math.ceil(length / K)
+        keep = [first] + self.inner_ckpt[level][:n - 1]
+        cur, spare = first, 0
+        for r in range(1, (n - 1) * K + 1):
+            if r % K == 0:
+                nxt = keep[r // K]
+            else:
+                nxt = self.tmp[spare]
+                spare ^= 1
+            self.lat.step_buf(cur, nxt)
+            cur = nxt
+        self.recompute_steps += (n - 1) * K
+        for m in range(n - 1, -1, -1):
+            yield from self._segment_reversed(keep[m], min(K, length - m * K), level + 1)
+
     def _states_reversed(self):
         """s_{T-1}, s_{T-2}, ..., s_0 (buffers valid until the next item)."""
-        lat = self.lat
         for j in range(self.n_ckpt - 1, -1, -1):
-            length = min(self.K, self.T - j * self.K)
-            if self.K2 is None:
-                yield from reversed(self._ring(self.ckpt[j], length))
-                continue
-            n2 = math.ceil(length / self.K2)
-            level2 = [self.ckpt[j]] + self.ckpt2[:n2 - 1]
-            cur, spare = self.ckpt[j], 0
-            for r in range(1, (n2 - 1) * self.K2 + 1):
-                if r % self.K2 == 0:
-                    nxt = level2[r // self.K2]
-                else:
-                    nxt = self.tmp[spare]
-                    spare ^= 1
-                lat.step_buf(cur, nxt)
-                cur = nxt
-            self.recompute_steps += (n2 - 1) * self.K2
-            for m in range(n2 - 1, -1, -1):
-                yield from reversed(self._ring(level2[m], min(self.K2, length - m * self.K2)))
+            yield from self._segment_reversed(self.ckpt[j], min(self.K, self.T - j * self.K), 0)
 
     def backward(self, dense=True):
         """Reverse sweep; returns (dL/ds0 dense [19,...], dL/dg dense [3,...]),

@@ -79,37 +79,50 @@ class FakeLattice:
         return None
 
 
-@pytest.mark.parametrize("T,K,K2", [(1, 1, None), (7, 3, None), (12, 5, None), (12, 12, None), (23, 5, 2),
-                                    (40, 10, 3), (41, 10, 4), (2000, 100, 10), (9, 4, 8)])
-def test_sweep_order_and_cost(T, K, K2):
+@pytest.mark.parametrize("T,iv", [(1, (1,)), (7, (3,)), (12, (5,)), (12, (12,)), (23, (5, 2)), (40, (10, 3)),
+                                  (41, (10, 4)), (2000, (100, 10)), (9, (4, 8)), (60, (20, 6, 2)), (61, (17, 5, 3)),
+                                  (2000, (200, 30, 6)), (10, (10, 3, 1))])
+def test_sweep_order_and_cost(T, iv):
     lat = FakeLattice()
-    run = CheckpointedAdjoint(lat, T, K, K2)
+    run = CheckpointedAdjoint(lat, T, *iv)
     run.forward(object())
     assert lat.steps == T and run.sT.t == T
     lat.steps = 0
     lam0, _ = run.backward()
     assert lat.seen == list(range(T - 1, -1, -1))
     assert lam0 == 0
-    assert run.recompute_steps == lat.steps == _recompute_cost(T, run.K, run.K2)
-    assert len(lat.states) == run.lattices() <= lattices_needed(T, K, K2)
+    assert run.recompute_steps == lat.steps == _recompute_cost(T, *run.intervals)
+    assert len(lat.states) == run.lattices() == lattices_needed(T, *iv)
     assert len(lat.adj) == 2
-    if run.K2 is None:
+    if len(run.intervals) == 1:
         assert run.recompute_steps == T - run.n_ckpt
+
+
+def _brute_best(T, budget, levels):
+    if levels == 1:
+        return min((_recompute_cost(T, k), (k,)) for k in range(1, T + 1) if lattices_needed(T, k) <= budget)
+    return min((_recompute_cost(T, k, k2), (k, k2)) for k in range(2, T + 1) for k2 in range(1, k)
+               if lattices_needed(T, k, k2) <= budget)
 
 
 @pytest.mark.parametrize("T,budget", [(2000, 100), (2000, 45), (2000, 40), (50, 12), (10, 8)])
 def test_plan_fits_and_is_no_worse_than_neighbours(T, budget):
-    K, K2 = plan_checkpoints(T, budget)
-    assert lattices_needed(T, K, K2) <= budget
-    cost = _recompute_cost(T, K, K2)
-    # brute force over every (K, K2) that fits, one level preferred
-    one = [k for k in range(1, T + 1) if lattices_needed(T, k) <= budget]
-    if one:
-        assert K2 is None and cost == min(_recompute_cost(T, k, None) for k in one)
+    iv = plan_checkpoints(T, budget)
+    assert lattices_needed(T, *iv) <= budget
+    cost = _recompute_cost(T, *iv)
+    if any(lattices_needed(T, k) <= budget for k in range(1, T + 1)):
+        assert len(iv) == 1 and cost == _brute_best(T, budget, 1)[0]
     else:
-        best = min(_recompute_cost(T, k, k2) for k in range(2, T + 1) for k2 in range(1, k)
-                   if lattices_needed(T, k, k2) <= budget)
-        assert cost == best
+        assert len(iv) == 2 and cost == _brute_best(T, budget, 2)[0]
+
+
+def test_plan_three_levels_when_two_do_not_fit():
+    T, budget = 2000, 30  # two levels need at least 38 lattices here
+    with pytest.raises(ValueError):
+        plan_checkpoints(T, budget, max_levels=2)
+    iv = plan_checkpoints(T, budget)
+    assert len(iv) == 3 and lattices_needed(T, *iv) <= budget
+    assert _recompute_cost(T, *iv) <= 3 * T
 
 
 def test_plan_rejects_impossible_budget():
@@ -120,4 +133,4 @@ def test_plan_rejects_impossible_budget():
 def test_one_level_cost_closed_form():
     for T in (1, 5, 17, 100):
         for K in (1, 2, 3, 7, 100):
-            assert _recompute_cost(T, min(K, T), None) == T - math.ceil(T / min(K, T))
+            assert _recompute_cost(T, min(K, T)) == T - math.ceil(T / min(K, T))

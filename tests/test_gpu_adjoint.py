@@ -229,7 +229,7 @@ def test_reverse_gather_is_transpose_of_pull_f32():
     assert np.array_equal(lat.adjoint_get(b).cpu().numpy(), O.pull_transpose(w, sp, periodic=7))
 
 
-def test_two_level_schedule_is_bitwise_one_level():
+def test_multi_level_schedules_are_bitwise_one_level():
     """The schedule only changes which forward states are recomputed when;
     the kernels are deterministic, so the gradients are bitwise equal."""
     import torch
@@ -240,10 +240,10 @@ def test_two_level_schedule_is_bitwise_one_level():
     f0 = torch.from_numpy(perturbed_state(sp, 9))
     g = torch.from_numpy(_force_field(sp, 10)).cuda()
     out = []
-    for K, K2 in ((5, None), (29, None), (10, 3), (12, 5)):
+    for iv in ((5,), (29,), (10, 3), (12, 5), (15, 6, 2)):
         lat = new_lattice(s, tau, 7)
         lat.set_force(g)
-        run = CheckpointedAdjoint(lat, T, K, K2)
+        run = CheckpointedAdjoint(lat, T, *iv)
         L = run.forward(f0)
         gs, gg = run.backward()
         out.append((L, gs.cpu().numpy(), gg.cpu().numpy()))

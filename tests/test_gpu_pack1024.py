@@ -46,7 +46,7 @@ def test_pack1024_f32_adjoint_directional_derivatives(pack):
     lat.set_force((G, 0.0, 0.0))
     lat.step(8000)
     run = CheckpointedAdjoint.within_memory(lat, T)
-    log(f"   checkpoints K={run.K} K2={run.K2} lattices={run.lattices()}")
+    log(f"   checkpoint intervals {run.intervals} lattices={run.lattices()}")
     L = run.forward(None)
     lam0, grad = run.backward(dense=False)
     torch.cuda.synchronize()
