@@ -93,8 +93,11 @@ def plan_checkpoints(T, max_lattices, max_levels=3):
     if max_levels < 2:
         raise ValueError(f"{T} adjoint steps do not fit in {M} lattices with one level")
     best = None
-    for K in range(2, T + 1):
-        if math.ceil(T / K) + 2 > M:
+    # every K for moderate T; for long horizons the K that start a new count
+    # of checkpoints (the search would otherwise take T * M cost evaluations)
+    ks = range(2, T + 1) if T <= 20000 else sorted({math.ceil(T / n) for n in range(1, M + 1)})
+    for K in ks:
+        if K < 2 or math.ceil(T / K) + 2 > M:
             continue
         for K2 in range(1, min(K, M)):
             if lattices_needed(T, K, K2) <= M:
