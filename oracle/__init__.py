@@ -4,9 +4,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product library never loads it and
 shares no code with it.
 
-The arithmetic lives in ``lbm_oracle.c`` (a dense D3Q19 LBGK step with pull
-streaming and halfway bounce-back, Guo forcing, macroscopic fields and a
-discrete adjoint) and in ``tiles_ref.py`` (the tiling of Alg. 1).  This module
+The arithmetic lives in ``lbm_oracle.c`` (a dense D3Q19 LBGK or
+multiple-relaxation-time step with pull streaming and halfway bounce-back, Guo
+forcing, macroscopic fields and a discrete adjoint) and in ``tiles_ref.py`` (the tiling of Alg. 1).  This module
 builds the C file with gcc and wraps it with numpy arrays; the reductions
 (mass, momentum, permeability) are numpy sums over the oracle's fields.
 """
@@ -62,6 +62,9 @@ def lib():
         L.oracle_loss_ux.restype = f64
         L.oracle_adjoint.argtypes = [P, P, i32, i32, i32, i32, f64, P, i32, P, P]
         L.oracle_adjoint.restype = f64
+        L.oracle_mrt_matrix.argtypes = [P, P]
+        L.oracle_mrt_rates.argtypes = [f64, P]
+        L.oracle_collide_mrt_rates.argtypes = [i32, P, P, P, P]
         _lib = L
     return _lib
 
@@ -99,6 +102,30 @@ def feq(rho, u, model=0):
 def guo(tau, u, F):
     out = np.zeros(Q)
     lib().oracle_guo(float(tau), _p(_f64(u)), _p(_f64(F)), _p(out))
+    return out
+
+
+MODELS = {"qc": 0, "inc": 1, "mrt-qc": 2, "mrt-inc": 3}
+
+
+def mrt_matrix():
+    """(M, M^-1): the D3Q19 moment matrix (rows = moments) and its inverse."""
+    M = np.zeros((Q, Q))
+    Minv = np.zeros((Q, Q))
+    lib().oracle_mrt_matrix(_p(M), _p(Minv))
+    return M, Minv
+
+
+def mrt_rates(tau):
+    s = np.zeros(Q)
+    lib().oracle_mrt_rates(float(tau), _p(s))
+    return s
+
+
+def collide_mrt_rates(fin, F, s, model=2):
+    """The multiple-relaxation-time operator with caller-given rates s[19]."""
+    out = np.zeros(Q)
+    lib().oracle_collide_mrt_rates(model, _p(_f64(fin)), _p(_f64(F)), _p(_f64(s)), _p(out))
     return out
 
 

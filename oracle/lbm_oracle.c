@@ -27,6 +27,7 @@
  * Arithmetic is plain C in double precision with the operations written in
  * the order of the formulas; build without FMA contraction.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -85,13 +86,19 @@ void oracle_lattice(int32_t *c /*[19][3]*/, double *w /*[19]*/, int32_t *opp /*[
 /* local pieces: equilibrium, forcing term, collision                  */
 /* ------------------------------------------------------------------ */
 
-/* Eq. 3 (model 0, quasi-compressible) or Eq. 4 (model 1, incompressible),
+/* Models: bit 0 selects the equilibrium and velocity (0 quasi-compressible,
+ * Eq. 3 and 5; 1 incompressible, Eq. 4 and 6), bit 1 the collision operator
+ * (0 single relaxation time, Eq. 2 and 7; 1 multiple relaxation times). */
+static int incompressible(int model) { return model & 1; }
+static int multi_relaxation(int model) { return (model >> 1) & 1; }
+
+/* Eq. 3 (quasi-compressible) or Eq. 4 (incompressible),
  * c_s^2 = 1/3 so 1/c_s^2 = 3, 1/(2 c_s^4) = 4.5, 1/(2 c_s^2) = 1.5 */
 static double feq_i(int model, int i, double rho, const double u[3]) {
     double cu = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
-    if (model == 0) return WT(i) * rho * (1.0 + poly);
+    if (!incompressible(model)) return WT(i) * rho * (1.0 + poly);
     return WT(i) * (rho + poly);
 }
 
@@ -113,15 +120,146 @@ static void moments(int model, const double fin[Q], const double F[3], double *r
         for (int a = 0; a < 3; ++a) j[a] += CV[i][a] * fin[i];
     }
     *rho = r;
-    for (int a = 0; a < 3; ++a) u[a] = (model == 0) ? (j[a] + 0.5 * F[a]) / r : (j[a] + 0.5 * F[a]);
+    for (int a = 0; a < 3; ++a) u[a] = !incompressible(model) ? (j[a] + 0.5 * F[a]) / r : (j[a] + 0.5 * F[a]);
 }
 
-/* Eq. 7 with the source: f*_i = f_i - (f_i - feq_i)/tau + S_i */
+/* ------------------------------------------------------------------ */
+/* multiple relaxation times (the LBMRT kernels of Sections 2.2 and    */
+/* 4.6; the paper names the operator but gives no matrix): the D3Q19   */
+/* moment basis of d'Humieres, Ginzburg, Krafczyk, Lallemand and Luo    */
+/* (2002), each moment a polynomial in the velocity c:                  */
+/*   rho, e, eps, j_x, q_x, j_y, q_y, j_z, q_z, 3p_xx, 3pi_xx, p_ww,    */
+/*   pi_ww, p_xy, p_yz, p_xz, m_x, m_y, m_z                             */
+/* ------------------------------------------------------------------ */
+static double mrt_row(int k, int i) {
+    const double cx = CV[i][0], cy = CV[i][1], cz = CV[i][2];
+    const double c2 = cx * cx + cy * cy + cz * cz;
+    switch (k) {
+    case 0: return 1.0;
+    case 1: return 19.0 * c2 - 30.0;
+    case 2: return (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+    case 3: return cx;
+    case 4: return (5.0 * c2 - 9.0) * cx;
+    case 5: return cy;
+    case 6: return (5.0 * c2 - 9.0) * cy;
+    case 7: return cz;
+    case 8: return (5.0 * c2 - 9.0) * cz;
+    case 9: return 3.0 * cx * cx - c2;
+    case 10: return (3.0 * cx * cx - c2) * (3.0 * c2 - 5.0);
+    case 11: return cy * cy - cz * cz;
+    case 12: return (cy * cy - cz * cz) * (3.0 * c2 - 5.0);
+    case 13: return cx * cy;
+    case 14: return cy * cz;
+    case 15: return cx * cz;
+    case 16: return (cy * cy - cz * cz) * cx;
+    case 17: return (cz * cz - cx * cx) * cy;
+    default: return (cx * cx - cy * cy) * cz;
+    }
+}
+
+/* relaxation rates of the same paper; the viscous moments relax at 1/tau
+ * (so nu = (tau - 1/2)/3 as for the single-time operator); the rates of the
+ * conserved moments (rho, j) do not enter */
+static void mrt_rates(double tau, double s[Q]) {
+    const double sv = 1.0 / tau;
+    const double r[Q] = {0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, sv, 1.4, sv, 1.4, sv, sv, sv, 1.98, 1.98, 1.98};
+    for (int k = 0; k < Q; ++k) s[k] = r[k];
+}
+
+/* M (rows k, columns i) and its inverse by Gauss-Jordan elimination, built
+ * once when the library is loaded (before any threaded loop can use them) */
+static double MRT_M[Q][Q], MRT_MINV[Q][Q];
+__attribute__((constructor)) static void mrt_init(void) {
+    double a[Q][2 * Q];
+    for (int k = 0; k < Q; ++k)
+        for (int i = 0; i < Q; ++i) {
+            MRT_M[k][i] = mrt_row(k, i);
+            a[k][i] = MRT_M[k][i];
+            a[k][Q + i] = (k == i) ? 1.0 : 0.0;
+        }
+    for (int col = 0; col < Q; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < Q; ++r)
+            if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
+        for (int c = 0; c < 2 * Q; ++c) {
+            double t = a[col][c];
+            a[col][c] = a[piv][c];
+            a[piv][c] = t;
+        }
+        const double p = a[col][col];
+        for (int c = 0; c < 2 * Q; ++c) a[col][c] /= p;
+        for (int r = 0; r < Q; ++r) {
+            if (r == col) continue;
+            const double m = a[r][col];
+            if (m != 0.0)
+                for (int c = 0; c < 2 * Q; ++c) a[r][c] -= m * a[col][c];
+        }
+    }
+    for (int i = 0; i < Q; ++i)
+        for (int k = 0; k < Q; ++k) MRT_MINV[i][k] = a[i][Q + k];
+}
+
+/* Guo source without its (1 - 1/(2 tau)) factor: w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)] */
+static double guo_raw_i(int i, const double u[3], const double F[3]) {
+    double cu = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
+    double cF = CV[i][0] * F[0] + CV[i][1] * F[1] + CV[i][2] * F[2];
+    double uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    return WT(i) * (3.0 * (cF - uF) + 9.0 * cu * cF);
+}
+
+/* m = M f, m_eq = M f_eq, m* = m - S (m - m_eq) + (I - S/2) M Fbar,
+ * f* = M^-1 m*  (Guo forcing carried into moment space) */
+static void collide_mrt_rates(int model, const double fin[Q], const double F[3], const double s[Q], double fout[Q]) {
+    double rho, u[3], fe[Q], fb[Q], m[Q], meq[Q], mf[Q], ms[Q];
+    moments(model, fin, F, &rho, u);
+    for (int i = 0; i < Q; ++i) {
+        fe[i] = feq_i(model, i, rho, u);
+        fb[i] = guo_raw_i(i, u, F);
+    }
+    for (int k = 0; k < Q; ++k) {
+        m[k] = meq[k] = mf[k] = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            m[k] += MRT_M[k][i] * fin[i];
+            meq[k] += MRT_M[k][i] * fe[i];
+            mf[k] += MRT_M[k][i] * fb[i];
+        }
+        ms[k] = m[k] - s[k] * (m[k] - meq[k]) + (1.0 - 0.5 * s[k]) * mf[k];
+    }
+    for (int i = 0; i < Q; ++i) {
+        fout[i] = 0.0;
+        for (int k = 0; k < Q; ++k) fout[i] += MRT_MINV[i][k] * ms[k];
+    }
+}
+
+/* Eq. 7 with the source: f*_i = f_i - (f_i - feq_i)/tau + S_i, or the
+ * multiple-relaxation-time operator */
 static void collide(int model, const double fin[Q], const double F[3], double tau, double fout[Q]) {
+    if (multi_relaxation(model)) {
+        double s[Q];
+        mrt_rates(tau, s);
+        collide_mrt_rates(model, fin, F, s, fout);
+        return;
+    }
     double rho, u[3];
     moments(model, fin, F, &rho, u);
     for (int i = 0; i < Q; ++i)
         fout[i] = fin[i] - (fin[i] - feq_i(model, i, rho, u)) / tau + guo_i(i, tau, u, F);
+}
+
+/* exports for the tests: the moment matrix, its inverse, the rates, and the
+ * operator with caller-given rates */
+void oracle_mrt_matrix(double *M /*[19][19]*/, double *Minv /*[19][19]*/) {
+    for (int k = 0; k < Q; ++k)
+        for (int i = 0; i < Q; ++i) {
+            M[k * Q + i] = MRT_M[k][i];
+            Minv[k * Q + i] = MRT_MINV[k][i];
+        }
+}
+
+void oracle_mrt_rates(double tau, double *s /*[19]*/) { mrt_rates(tau, s); }
+
+void oracle_collide_mrt_rates(int32_t model, const double *fin, const double *F, const double *s, double *fout) {
+    collide_mrt_rates(model, fin, F, s, fout);
 }
 
 void oracle_feq(int32_t model, double rho, const double *u, double *feq /*[19]*/) {
@@ -279,7 +417,8 @@ void oracle_macroscopic(const double *f, const uint8_t *solid, int32_t nx, int32
         }
         force_at(force, N, n, fx, fy, fz, F);
         rho[n] = r;
-        for (int a = 0; a < 3; ++a) u[(long)a * N + n] = (model == 0) ? (j[a] - 0.5 * F[a]) / r : (j[a] - 0.5 * F[a]);
+        for (int a = 0; a < 3; ++a)
+            u[(long)a * N + n] = !incompressible(model) ? (j[a] - 0.5 * F[a]) / r : (j[a] - 0.5 * F[a]);
     }
 }
 
