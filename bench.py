@@ -59,10 +59,10 @@ def build_case(args):
     return solid
 
 
-def time_storage(solid, storage, args, torch, want_state=False):
+def time_storage(solid, storage, args, torch, want_state=False, model="qc"):
     from paper_1611_02445_amd.lattice import Lattice
     # "f32u": FP32 storage of f itself (the paper's form), an ablation of the shift
-    lat = Lattice(solid, args.tau, periodic=7, storage="f32" if storage == "f32u" else storage,
+    lat = Lattice(solid, args.tau, periodic=7, storage="f32" if storage == "f32u" else storage, model=model,
                   tiles_per_wg=args.tpw, tile_order=args.order, f32_unshifted=storage == "f32u")
     lat.init()
     lat.set_force((args.g, 0.0, 0.0))
@@ -270,7 +270,7 @@ def sweep_sphere_arrays(args, torch):
         solid, _ = inputs.sphere_pack((192, 192, 192), p, 20.0, 20.0, seed=11)
         row = {"porosity": p}
         for st in ("f64", "f32"):
-            for model in ("inc", "qc"):
+            for model in ("inc", "qc", "mrt-inc", "mrt-qc"):
                 lat = Lattice(solid, 0.7, periodic=7, storage=st, model=model)
                 lat.init()
                 lat.set_force((1e-6, 0.0, 0.0))
@@ -475,6 +475,20 @@ def main():
         del rv
     if variants:
         result["variants"] = variants
+    # the paper's LBMRT kernels: multiple relaxation times, same tiles and bytes
+    mrt = {}
+    for st in ("f64", "f32"):
+        a2 = argparse.Namespace(**vars(args))
+        a2.steps = min(args.steps, 1000)
+        rm = time_storage(solid, st, a2, torch, model="mrt-qc")
+        ms = rm["gpu_ms"] / a2.steps
+        mf = nf * a2.steps / (rm["gpu_ms"] / 1e3) / 1e6
+        mrt[st] = {"MFLUPS": round(mf, 2), "ms_per_step": round(ms, 6),
+                   "hbm_frac": round(BYTES_PER_UPDATE[st] * nf / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "permeability": rm["k"]}
+        log(f"[bench] mrt {st}: {mf:.1f} MFLUPS")
+        del rm
+    result["mrt_quasi_compressible"] = mrt
     del r, lat
     torch.cuda.empty_cache()
     if args.adj_steps > 0:

@@ -52,7 +52,17 @@ typedef enum {
 } lbm_status;
 
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2 } lbm_storage;
-typedef enum { LBM_QUASI_COMPRESSIBLE = 0, LBM_INCOMPRESSIBLE = 1 } lbm_model;
+/* Collision models: bit 0 picks the equilibrium and velocity (Eq. 3 and 5,
+ * or Eq. 4 and 6), bit 1 the operator: single relaxation time (LBGK, Eq. 2
+ * and 7) or multiple relaxation times (the paper's LBMRT; D3Q19 moment basis
+ * and rates of d'Humieres et al. 2002, viscous moments relaxed at 1/tau, Guo
+ * forcing in moment space). */
+typedef enum {
+    LBM_QUASI_COMPRESSIBLE = 0,
+    LBM_INCOMPRESSIBLE = 1,
+    LBM_MRT_QUASI_COMPRESSIBLE = 2,
+    LBM_MRT_INCOMPRESSIBLE = 3
+} lbm_model;
 enum { LBM_PX = 1, LBM_PY = 2, LBM_PZ = 4 }; /* periodic-axis bits */
 
 /* ------------------------------------------------------------------------
@@ -97,7 +107,7 @@ typedef struct lbm_params {
     double tau;             /* LBGK relaxation time (Eq. 2), > 1/2; nu = (tau - 1/2)/3 */
     double rho0;            /* reference density: F = rho0 * g, shift of reduced storage */
     int32_t storage;        /* lbm_storage */
-    int32_t model;          /* lbm_model: Eq. 3+5 (0) or Eq. 4+6 (1) */
+    int32_t model;          /* lbm_model */
     int32_t f16_log2_scale; /* LBM_F16S: stored h = fp16(2^k (f_i - w_i rho0)), k in [0, 30] */
     int32_t tiles_per_wg;   /* tiles (wave64s) per workgroup: 1, 2, 4 or 8; 0 = default */
     int32_t f16_rounding;   /* LBM_F16S stores: 0 = stochastic (unbiased; default), 1 = nearest-even.

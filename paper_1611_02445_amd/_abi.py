@@ -13,7 +13,7 @@ LBM_OK = 0
 STATUS = {0: "LBM_OK", -1: "LBM_E_INVAL", -2: "LBM_E_NOMEM", -3: "LBM_E_RANGE", -4: "LBM_E_HIP",
           -5: "LBM_E_STATE", -6: "LBM_E_UNSUPPORTED", -7: "LBM_E_NUMERIC"}
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2}
-MODEL = {"qc": 0, "quasi-compressible": 0, "inc": 1, "incompressible": 1}
+MODEL = {"qc": 0, "quasi-compressible": 0, "inc": 1, "incompressible": 1, "mrt-qc": 2, "mrt-inc": 3}
 
 # every symbol include/lbm.h declares
 EXPORTS = [

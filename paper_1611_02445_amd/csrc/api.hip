@@ -48,7 +48,7 @@ int check_params(const lbm_params *p) {
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_E_INVAL, "tau must be > 1/2 (got %g)", p->tau);
     if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LBM_E_INVAL, "rho0 must be > 0 (got %g)", p->rho0);
     if (p->storage < LBM_F64 || p->storage > LBM_F16S) return fail(LBM_E_INVAL, "unknown storage %d", p->storage);
-    if (p->model != LBM_QUASI_COMPRESSIBLE && p->model != LBM_INCOMPRESSIBLE)
+    if (p->model < LBM_QUASI_COMPRESSIBLE || p->model > LBM_MRT_INCOMPRESSIBLE)
         return fail(LBM_E_INVAL, "unknown model %d", p->model);
     if (p->f16_log2_scale < 0 || p->f16_log2_scale > 30)
         return fail(LBM_E_INVAL, "f16_log2_scale must be in [0, 30] (got %d)", p->f16_log2_scale);
@@ -411,7 +411,7 @@ extern "C" int lbm_tiles_to_dense(lbm_ctx *c, const void *tile_buf, int32_t ncom
 static int adjoint_supported(lbm_ctx *c) {
     if (c->params.storage == LBM_F16S) return fail(LBM_E_UNSUPPORTED, "adjoint: built for FP64 and FP32 storage only");
     if (c->params.model != LBM_QUASI_COMPRESSIBLE)
-        return fail(LBM_E_UNSUPPORTED, "adjoint: only the quasi-compressible model is built");
+        return fail(LBM_E_UNSUPPORTED, "adjoint: built for the quasi-compressible LBGK model only");
     return LBM_OK;
 }
 

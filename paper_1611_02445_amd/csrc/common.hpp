@@ -32,6 +32,67 @@ constexpr int opposite(int i) {
 }
 constexpr double weight(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
+// multiple relaxation times: moment k of direction i, the D3Q19 basis of
+// d'Humieres, Ginzburg, Krafczyk, Lallemand and Luo (2002) written as
+// polynomials of c (rho, e, eps, j_x, q_x, j_y, q_y, j_z, q_z, 3p_xx, 3pi_xx,
+// p_ww, pi_ww, p_xy, p_yz, p_xz, m_x, m_y, m_z); the rows are orthogonal
+constexpr int mrt_coef(int k, int i) {
+    const int cx = CX[i], cy = CY[i], cz = CZ[i];
+    const int c2 = cx * cx + cy * cy + cz * cz;
+    switch (k) {
+    case 0: return 1;
+    case 1: return 19 * c2 - 30;
+    case 2: return (21 * c2 * c2 - 53 * c2 + 24) / 2;
+    case 3: return cx;
+    case 4: return (5 * c2 - 9) * cx;
+    case 5: return cy;
+    case 6: return (5 * c2 - 9) * cy;
+    case 7: return cz;
+    case 8: return (5 * c2 - 9) * cz;
+    case 9: return 3 * cx * cx - c2;
+    case 10: return (3 * cx * cx - c2) * (3 * c2 - 5);
+    case 11: return cy * cy - cz * cz;
+    case 12: return (cy * cy - cz * cz) * (3 * c2 - 5);
+    case 13: return cx * cy;
+    case 14: return cy * cz;
+    case 15: return cx * cz;
+    case 16: return (cy * cy - cz * cz) * cx;
+    case 17: return (cz * cz - cx * cx) * cy;
+    default: return (cx * cx - cy * cy) * cz;
+    }
+}
+constexpr int mrt_norm(int k) {
+    int n = 0;
+    for (int i = 0; i < Q; ++i) n += mrt_coef(k, i) * mrt_coef(k, i);
+    return n;
+}
+// the same as a table, evaluated by the compiler
+struct MrtTable {
+    int c[Q][Q];
+    int n[Q];
+};
+constexpr MrtTable make_mrt_table() {
+    MrtTable t{};
+    for (int k = 0; k < Q; ++k) {
+        for (int i = 0; i < Q; ++i) t.c[k][i] = mrt_coef(k, i);
+        t.n[k] = mrt_norm(k);
+    }
+    return t;
+}
+constexpr MrtTable MRT = make_mrt_table();
+// relaxation rate of moment k; 0 marks the conserved moments (rho, j), whose
+// non-equilibrium part vanishes; -1 marks the viscous moments (rate 1/tau)
+constexpr double mrt_rate(int k) {
+    switch (k) {
+    case 0: case 3: case 5: case 7: return 0.0;
+    case 1: return 1.19;
+    case 2: case 10: case 12: return 1.4;
+    case 4: case 6: case 8: return 1.2;
+    case 16: case 17: case 18: return 1.98;
+    default: return -1.0;
+    }
+}
+
 // lane n = x + 4y + 16z inside a tile (the XYZ map of Eq. 11)
 constexpr int TILE = 64;
 

@@ -460,6 +460,76 @@ __device__ __forceinline__ void collide(T (&d)[Q], T rho_base, T omega, T kg, T 
     }
 }
 
+// ---------------------------------------------------------------------------
+// multiple relaxation times (the paper's LBMRT), on shifted values: with
+// r_i = d_i - deq_i and the Guo source G_i = w_i (3 (c_i - u).F + 9 (c_i.u)(c_i.F)),
+//   m* = m - S (m - m_eq) + (I - S/2) M G,  f* = M^-1 m*
+// is, in distribution space,
+//   d*_i = d_i + G_i - [M^-1 S M (r + G/2)]_i,
+// and M^-1 = M^T diag(1/|row|^2) since the rows are orthogonal.  The
+// conserved moments (rate 0) drop out: their part of r + G/2 is zero.
+// ---------------------------------------------------------------------------
+template <typename T, int INC>
+__device__ __forceinline__ void collide_mrt(T (&d)[Q], T rho_base, T omega, T Fx, T Fy, T Fz) {
+    T drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        drho += d[i];
+        if (CX[i]) jx += CX[i] > 0 ? d[i] : -d[i];
+        if (CY[i]) jy += CY[i] > 0 ? d[i] : -d[i];
+        if (CZ[i]) jz += CZ[i] > 0 ? d[i] : -d[i];
+    }
+    const T rho = rho_base + drho;
+    T ux = jx + T(0.5) * Fx, uy = jy + T(0.5) * Fy, uz = jz + T(0.5) * Fz;
+    if constexpr (!INC) {
+        const T ir = T(1) / rho;
+        ux *= ir;
+        uy *= ir;
+        uz *= ir;
+    }
+    const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
+    const T uF3 = T(3) * (ux * Fx + uy * Fy + uz * Fz);
+    const T bscale = INC ? T(1) : rho;
+    T v[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T w = T(weight(i));
+        const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
+        const T cF = T(CX[i]) * Fx + T(CY[i]) * Fy + T(CZ[i]) * Fz;
+        const T deq = w * (drho + bscale * (T(3) * cu + T(4.5) * cu * cu - usq));
+        const T src = w * (T(3) * cF - uF3 + T(9) * cu * cF);
+        v[i] = d[i] - deq + T(0.5) * src;
+        d[i] += src;  // d_i + G_i; the relaxation is subtracted below
+    }
+    T mu[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        mu[k] = T(0);
+        if (mrt_rate(k) == 0.0) continue;
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            if (MRT.c[k][i]) acc += T(MRT.c[k][i]) * v[i];
+        const T rate = mrt_rate(k) < 0.0 ? omega : T(mrt_rate(k));
+        mu[k] = acc * (rate * T(1.0 / MRT.n[k]));
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T acc = T(0);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+            if (mrt_rate(k) != 0.0 && MRT.c[k][i]) acc += T(MRT.c[k][i]) * mu[k];
+        d[i] -= acc;
+    }
+}
+
+// the collision of a model: LBGK (0, 1) or multiple relaxation times (2, 3)
+template <typename T, int MODEL>
+__device__ __forceinline__ void collide_model(T (&d)[Q], T rho_base, T omega, T kg, T Fx, T Fy, T Fz) {
+    if constexpr (MODEL >= LBM_MRT_QUASI_COMPRESSIBLE) collide_mrt<T, (MODEL & 1)>(d, rho_base, omega, Fx, Fy, Fz);
+    else collide<T, MODEL>(d, rho_base, omega, kg, Fx, Fy, Fz);
+}
+
 struct KArgs {
     const char *src;
     char *dst;
@@ -517,7 +587,7 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
         for (int i = 0; i < Q; ++i) d[i] = C::dec(raw[i], a.P.inv_scale);
         T Fx, Fy, Fz;
         load_force<T>(a.P, t, lane, Fx, Fy, Fz);
-        collide<T, MODEL>(d, T(a.P.rho_base), T(a.P.omega), T(a.P.kg), Fx, Fy, Fz);
+        collide_model<T, MODEL>(d, T(a.P.rho_base), T(a.P.omega), T(a.P.kg), Fx, Fy, Fz);
     }
     if constexpr (ST == LBM_F16S) {
         if (a.P.f16_stochastic) {
@@ -580,7 +650,7 @@ __global__ __launch_bounds__(512) void k_init(KArgs a, char *b, double ux, doubl
     auto feq = [&](int i) {
         const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
         const double P = 3.0 * cu + 4.5 * cu * cu - usq;
-        const double f = (a.P.model == LBM_QUASI_COMPRESSIBLE) ? weight(i) * rho * (1.0 + P) : weight(i) * (rho + P);
+        const double f = (a.P.model & 1) ? weight(i) * (rho + P) : weight(i) * rho * (1.0 + P);
         return C::enc((typename C::T)(f - weight(i) * a.P.rho_base), a.P.scale);
     };
     if constexpr (C::RUNS) {
@@ -650,7 +720,7 @@ __global__ __launch_bounds__(512) void k_macro(KArgs a, double *rho_out, double 
     const double rho = a.P.rho_base + drho;
     const double mx = jx - 0.5 * (double)Fx, my = jy - 0.5 * (double)Fy, mz = jz - 0.5 * (double)Fz;
     double ux = mx, uy = my, uz = mz;
-    if (a.P.model == LBM_QUASI_COMPRESSIBLE) {
+    if (!(a.P.model & 1)) {  // quasi-compressible velocity (either operator)
         ux = mx / rho;
         uy = my / rho;
         uz = mz / rho;
@@ -994,14 +1064,24 @@ static hipError_t step_t(const Launch &L, const KArgs &a) {
     return hipGetLastError();
 }
 
+template <int ST>
+static hipError_t step_st(const Launch &L, const KArgs &a, int model) {
+    switch (model) {
+    case LBM_QUASI_COMPRESSIBLE: return step_t<ST, LBM_QUASI_COMPRESSIBLE>(L, a);
+    case LBM_INCOMPRESSIBLE: return step_t<ST, LBM_INCOMPRESSIBLE>(L, a);
+    case LBM_MRT_QUASI_COMPRESSIBLE: return step_t<ST, LBM_MRT_QUASI_COMPRESSIBLE>(L, a);
+    case LBM_MRT_INCOMPRESSIBLE: return step_t<ST, LBM_MRT_INCOMPRESSIBLE>(L, a);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_step(const Launch &L, const Phys &P, const void *src, void *dst) {
     if (L.n_tiles == 0) return hipSuccess;
     const KArgs a = make_args(L, P, src, dst);
-    const bool inc = P.model == LBM_INCOMPRESSIBLE;
     switch (P.storage) {
-    case LBM_F64: return inc ? step_t<LBM_F64, LBM_INCOMPRESSIBLE>(L, a) : step_t<LBM_F64, LBM_QUASI_COMPRESSIBLE>(L, a);
-    case LBM_F32: return inc ? step_t<LBM_F32, LBM_INCOMPRESSIBLE>(L, a) : step_t<LBM_F32, LBM_QUASI_COMPRESSIBLE>(L, a);
-    case LBM_F16S: return inc ? step_t<LBM_F16S, LBM_INCOMPRESSIBLE>(L, a) : step_t<LBM_F16S, LBM_QUASI_COMPRESSIBLE>(L, a);
+    case LBM_F64: return step_st<LBM_F64>(L, a, P.model);
+    case LBM_F32: return step_st<LBM_F32>(L, a, P.model);
+    case LBM_F16S: return step_st<LBM_F16S>(L, a, P.model);
     }
     return hipErrorInvalidValue;
 }

@@ -27,7 +27,7 @@ def _run_case(name, solid, periodic, tau, steps, g=(0.0, 0.0, 0.0), model="qc", 
         f0 = perturbed_state(sp, seed)
         lat.set_state(torch.from_numpy(f0))
     else:
-        f0 = O.init(sp, model=0 if model == "qc" else 1)
+        f0 = O.init(sp, model=O.MODELS[model])
     if field is not None:
         lat.set_force(torch.from_numpy(field))
         force = field  # oracle takes F = rho0 g with rho0 = 1
@@ -37,7 +37,7 @@ def _run_case(name, solid, periodic, tau, steps, g=(0.0, 0.0, 0.0), model="qc", 
     lat.step(steps)
     torch.cuda.synchronize()
     fg = lat.get_state().cpu().numpy()
-    fo = O.run(f0, sp, tau, steps, force=force, periodic=periodic, model=0 if model == "qc" else 1)
+    fo = O.run(f0, sp, tau, steps, force=force, periodic=periodic, model=O.MODELS[model])
     err = rel_err_f(fg, fo, sp)
     log(f"   f rel err {err:.3e}  tiles={lat.n_tiles} fluid={lat.n_fluid}")
     assert err <= TOL
@@ -93,6 +93,17 @@ def test_mixed_periodicity_random_bitmap():
 def test_incompressible_model():
     s, _ = I.sphere_pack((16, 16, 16), 0.6, 2.0, 4.0, seed=8)
     _run_case("incompressible", s, 7, 0.75, 100, g=(1e-5, 0, 0), model="inc", seed=5)
+
+
+@pytest.mark.parametrize("model", ["mrt-qc", "mrt-inc"])
+def test_multiple_relaxation_times(model):
+    s, _ = I.sphere_pack((20, 16, 24), 0.55, 2.0, 4.5, seed=12)
+    _run_case(model, s, 7, 0.68, 100, g=(1e-5, -2e-6, 3e-6), model=model, seed=6)
+
+
+def test_multiple_relaxation_times_ragged_nonperiodic():
+    s, _ = I.sphere_pack((21, 18, 27), 0.5, 2.0, 5.0, seed=13, periodic=False)
+    _run_case("mrt-ragged", s, 0, 0.9, 60, g=(2e-5, 1e-5, 0), model="mrt-qc", seed=7)
 
 
 def test_per_node_force_field():

@@ -33,7 +33,8 @@ def _run(solid, tau, periodic, storage, steps, g, f0=None, **kw):
 
 
 @pytest.mark.parametrize("storage,model", [("f32", "qc"), ("f16s", "qc"), ("f32", "inc"), ("f16s", "inc"),
-                                           ("f32u", "qc")])
+                                           ("f32u", "qc"), ("f32", "mrt-qc"), ("f16s", "mrt-qc"),
+                                           ("f32", "mrt-inc")])
 def test_reduced_storage_against_oracle(storage, model):
     tau, steps, g = 0.7, 100, (1e-5, 2e-6, 0.0)
     s, _ = I.sphere_pack((24, 24, 24), 0.5, 2.0, 5.0, seed=51)
@@ -44,7 +45,7 @@ def test_reduced_storage_against_oracle(storage, model):
         kw["f32_unshifted"] = True
     lat = _run(s, tau, 7, "f32" if storage == "f32u" else storage, steps, g, f0=f0, **kw)
     got = lat.get_state().cpu().numpy()
-    ref = O.run(f0, sp, tau, steps, force=np.array(g), periodic=7, model={"qc": 0, "inc": 1}[model])
+    ref = O.run(f0, sp, tau, steps, force=np.array(g), periodic=7, model=O.MODELS[model])
     fl = sp == 0
     c, w, _ = O.lattice()
     shift = 0.0 if storage == "f32u" else 1.0
