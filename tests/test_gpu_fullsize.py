@@ -12,13 +12,14 @@ from helpers import log, new_lattice, padded
 pytestmark = pytest.mark.gpu
 
 
-def test_sphere_pack_256_sampled_nodes_and_mass():
+@pytest.mark.parametrize("model", ["qc", "mrt-qc"])
+def test_sphere_pack_256_sampled_nodes_and_mass(model):
     import torch
     tau, g = 0.7, 1e-6
     s, n_sph = I.sphere_pack((256, 256, 256), 0.4, 4.0, 12.0, seed=2)
-    log(f"[case] spheres256 spheres={n_sph}")
+    log(f"[case] spheres256 spheres={n_sph} model={model}")
     sp = padded(s, 7)
-    lat = new_lattice(s, tau, 7)
+    lat = new_lattice(s, tau, 7, model=model)
     lat.init()
     lat.set_force((g, 0, 0))
     _, _, s0 = lat.macroscopic(fields=False)
@@ -30,7 +31,7 @@ def test_sphere_pack_256_sampled_nodes_and_mass():
     rng = np.random.default_rng(0)
     fluid = np.flatnonzero(sp.ravel() == 0)
     nodes = rng.choice(fluid, 4096, replace=False)
-    ref = O.step_nodes(prev, sp, tau, nodes, force=[g, 0, 0], periodic=7)
+    ref = O.step_nodes(prev, sp, tau, nodes, force=[g, 0, 0], periodic=7, model=O.MODELS[model])
     got = cur.reshape(19, -1)[:, nodes].T
     err = np.max(np.abs(got - ref) / np.abs(ref))
     log(f"   sampled f rel err {err:.3e}; mass drift {(s1[0] - s0[0]) / s0[0]:.3e}")
