@@ -290,6 +290,56 @@ def sweep_sphere_arrays(args, torch):
     return rows
 
 
+def sweep_channels(args, torch):
+    """The paper's propagation study (Section 4.4, Eqs. 17-19) on this GPU:
+    fully fluid rectangular channels of ~2^24 nodes (walls by bounce-back),
+    from 4 x 4 x L to 256 x 256 x 256, timed with the propagation-only kernel.
+    eta_f / eta_e = common tile faces / edges per tile."""
+    from paper_1611_02445_amd.lattice import Lattice
+    N = 1 << 24
+    rows = []
+    sides = (4, 8, 16, 32, 64, 128, 256)
+    for a in sides:
+        for b in sides:
+            if b < a:
+                continue
+            c = max(4, (N // (a * b)) // 4 * 4)
+            if c < b:
+                continue
+            A, B, C = a // 4, b // 4, c // 4
+            T = A * B * C
+            eta_f = ((A - 1) * B * C + A * (B - 1) * C + A * B * (C - 1)) / T
+            eta_e = ((A - 1) * (B - 1) * C + (A - 1) * B * (C - 1) + A * (B - 1) * (C - 1)) / T
+            solid = np.zeros((c, b, a), dtype=np.uint8)
+            lat = Lattice(solid, 0.7, periodic=0)
+            lat.init()
+            x, y = lat.new_state(), lat.new_state()
+            x.copy_(lat.current_state())
+            for _ in range(10):
+                lat.calib_step(2, x, y)
+                x, y = y, x
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(lat.stream)
+            for _ in range(100):
+                lat.calib_step(2, x, y)
+                x, y = y, x
+            ev1.record(lat.stream)
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / 100
+            mf = lat.n_fluid / (ms / 1e3) / 1e6
+            rows.append({"dims": [a, b, c], "eta_f": round(eta_f, 4), "eta_e": round(eta_e, 4),
+                         "MFLUPS": round(mf, 1),
+                         "bw_util": round(mf * 1e6 * BYTES_PER_UPDATE["f64"] / (HBM_PEAK_GBS * 1e9), 4)})
+            log(f"[bench] channel {a}x{b}x{c}: eta_f {eta_f:.3f} eta_e {eta_e:.3f} "
+                f"{mf:.0f} MFLUPS, {rows[-1]['bw_util']:.3f}")
+            del lat, x, y
+    X = np.array([[1.0, r["eta_f"], r["eta_e"]] for r in rows])
+    yv = np.array([r["bw_util"] for r in rows])
+    coef = np.linalg.lstsq(X, yv, rcond=None)[0]
+    return {"rows": rows, "plane_fit": {"bw_util_at_0": round(float(coef[0]), 4),
+                                        "per_face": round(float(coef[1]), 5), "per_edge": round(float(coef[2]), 5)}}
+
+
 def cpu_baseline(solid, args):
     """The oracle as it stands, on the same geometry, for a bounded number of
     steps (about --cpu-seconds of CPU work)."""
@@ -336,6 +386,8 @@ def main():
                     help="also run the 1024x512x512 FP32 forward + adjoint workload (about 2 minutes)")
     ap.add_argument("--sweep192", action="store_true",
                     help="also time the step on 192^3 random sphere arrays at porosities 0.9..0.1")
+    ap.add_argument("--sweep-channels", action="store_true",
+                    help="also time the propagation-only kernel on rectangular channels (the paper's Eqs. 17-19 study)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -499,6 +551,9 @@ def main():
         torch.cuda.empty_cache()
     if args.sweep192:
         result["sphere_arrays_192"] = sweep_sphere_arrays(args, torch)
+        torch.cuda.empty_cache()
+    if args.sweep_channels:
+        result["channels_propagation"] = sweep_channels(args, torch)
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
