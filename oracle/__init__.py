@@ -65,6 +65,8 @@ def lib():
         L.oracle_mrt_matrix.argtypes = [P, P]
         L.oracle_mrt_rates.argtypes = [f64, P]
         L.oracle_collide_mrt_rates.argtypes = [i32, P, P, P, P]
+        L.oracle_zou_he.argtypes = [i32, i32, P, f64, P, P]
+        L.oracle_run_bc.argtypes = [P, P, P, i32, i32, i32, i32, i32, f64, P, f64, f64, f64, i32, P, P, f64]
         _lib = L
     return _lib
 
@@ -127,6 +129,28 @@ def collide_mrt_rates(fin, F, s, model=2):
     out = np.zeros(Q)
     lib().oracle_collide_mrt_rates(model, _p(_f64(fin)), _p(_f64(F)), _p(_f64(s)), _p(out))
     return out
+
+
+def zou_he(f, btype, u_in=(0.0, 0.0, 0.0), rho_out=1.0, F=(0.0, 0.0, 0.0), model=0):
+    """The populations of one node after the open-boundary rebuild
+    (btype 1 velocity inlet, 2 pressure outlet)."""
+    out = _f64(f).copy()
+    lib().oracle_zou_he(int(btype), int(model), _p(_f64(u_in)), float(rho_out), _p(_f64(F)), _p(out))
+    return out
+
+
+def run_bc(f, solid, tau, nsteps, btype, u_in=(0.0, 0.0, 0.0), rho_out=1.0, force=None, periodic=0, model=0):
+    """nsteps steps with open boundaries: btype [nz,ny,nx] uint8 (0 none,
+    1 velocity inlet u_in, 2 pressure outlet rho_out)."""
+    solid = _u8(solid)
+    nz, ny, nx = solid.shape
+    fa = _f64(f).copy()
+    scratch = np.zeros_like(fa)
+    keep, fp, fx, fy, fz = _force_args(force)
+    bt = _u8(btype)
+    lib().oracle_run_bc(_p(fa), _p(scratch), _p(solid), nx, ny, nz, periodic, model, tau, fp, fx, fy, fz,
+                        int(nsteps), _p(bt), _p(_f64(u_in)), float(rho_out))
+    return fa
 
 
 def collide_node(fin, F, tau, model=0):

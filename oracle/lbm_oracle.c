@@ -324,6 +324,67 @@ static void gather(const box_t *b, const double *s, long N, int x, int y, int z,
 }
 
 /* ------------------------------------------------------------------ */
+/* open boundaries (the paper's Zou-He velocity inlet and constant-     */
+/* pressure outlet, Section 2.2) on faces normal to x: after the gather, */
+/* the populations that enter through the face are rebuilt so that the   */
+/* node has the prescribed velocity (inlet) or density (outlet).          */
+/* Types: 1 = velocity inlet, the domain lies at +x (unknown: c_x = +1); */
+/* 2 = pressure outlet, the domain lies at -x (unknown: c_x = -1).       */
+/* With a body force the rebuilt momentum is J = rho u - F/2, so that    */
+/* the collision's velocity (J + F/2)/rho is the prescribed one; the     */
+/* outlet's tangential velocity is 0.                                     */
+/* Unknown i (c_ix = n) from its opposite, Zou and He's bounce-back of   */
+/* the non-equilibrium part with the tangential-momentum correction of   */
+/* Hecht and Harting (2010):                                              */
+/*   f_i = f_opp(i) + 6 w_i (c_i . J) - sum_t c_it N_t,                  */
+/*   N_t = 1/2 sum_{c_x = 0} c_t f - J_t / 3   (t = y, z)                */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    const uint8_t *type; /* [N] 0 none, 1 inlet, 2 outlet; NULL = no open boundaries */
+    double u[3];         /* inlet velocity */
+    double rho_out;      /* outlet density */
+} bc_t;
+
+static void zou_he(int type, int model, const double u_in[3], double rho_out, const double F[3], double f[Q]) {
+    const int n = (type == 1) ? 1 : -1; /* c_x of the unknown populations */
+    double s_tan = 0.0, s_in = 0.0, t[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        if (CV[i][0] == 0) {
+            s_tan += f[i];
+            t[1] += CV[i][1] * f[i];
+            t[2] += CV[i][2] * f[i];
+        } else if (CV[i][0] == -n) {
+            s_in += f[i]; /* the populations leaving through the face, known */
+        }
+    }
+    double J[3];
+    if (type == 1) {
+        if (!incompressible(model)) {
+            const double rho = (s_tan + 2.0 * s_in - 0.5 * n * F[0]) / (1.0 - n * u_in[0]);
+            for (int a = 0; a < 3; ++a) J[a] = rho * u_in[a] - 0.5 * F[a];
+        } else {
+            for (int a = 0; a < 3; ++a) J[a] = u_in[a] - 0.5 * F[a];
+        }
+    } else {
+        /* sum f = rho_out and sum c_x f = J_x fix the normal momentum */
+        J[0] = n * (rho_out - s_tan - 2.0 * s_in);
+        J[1] = -0.5 * F[1];
+        J[2] = -0.5 * F[2];
+    }
+    const double N1 = 0.5 * t[1] - J[1] / 3.0, N2 = 0.5 * t[2] - J[2] / 3.0;
+    for (int i = 0; i < Q; ++i) {
+        if (CV[i][0] != n) continue;
+        const double cJ = CV[i][0] * J[0] + CV[i][1] * J[1] + CV[i][2] * J[2];
+        f[i] = f[OPP(i)] + 6.0 * WT(i) * cJ - CV[i][1] * N1 - CV[i][2] * N2;
+    }
+}
+
+/* exported for the tests: the rebuilt populations of one node */
+void oracle_zou_he(int32_t type, int32_t model, const double *u_in, double rho_out, const double *F, double *f) {
+    zou_he(type, model, u_in, rho_out, F, f);
+}
+
+/* ------------------------------------------------------------------ */
 /* initial state, one step, macroscopic fields                         */
 /* ------------------------------------------------------------------ */
 
@@ -338,12 +399,12 @@ void oracle_init(double *f, const uint8_t *solid, int32_t nx, int32_t ny, int32_
     }
 }
 
-/* one time step: fb = C(S fa).  Solid nodes are neither read (bounce-back
- * replaces the read) nor written.  force: NULL for the uniform (fx,fy,fz),
- * otherwise a per-node field [3][N]. */
-void oracle_step(const double *fa, double *fb, const uint8_t *solid, int32_t nx, int32_t ny, int32_t nz,
-                 int32_t periodic, int32_t model, double tau, const double *force, double fx, double fy,
-                 double fz) {
+/* one time step: fb = C(S fa), with open boundaries when bc->type is set.
+ * Solid nodes are neither read (bounce-back replaces the read) nor written.
+ * force: NULL for the uniform (fx,fy,fz), otherwise a per-node field [3][N]. */
+static void step_bc(const double *fa, double *fb, const uint8_t *solid, int32_t nx, int32_t ny, int32_t nz,
+                    int32_t periodic, int32_t model, double tau, const double *force, double fx, double fy,
+                    double fz, const bc_t *bc) {
     box_t b = {nx, ny, nz, periodic, solid};
     long N = (long)nx * ny * nz;
 #pragma omp parallel for schedule(static)
@@ -355,9 +416,32 @@ void oracle_step(const double *fa, double *fb, const uint8_t *solid, int32_t nx,
                 double fin[Q], fout[Q], F[3];
                 gather(&b, fa, N, x, y, z, fin);
                 force_at(force, N, idx, fx, fy, fz, F);
+                if (bc && bc->type && bc->type[idx]) zou_he(bc->type[idx], model, bc->u, bc->rho_out, F, fin);
                 collide(model, fin, F, tau, fout);
                 for (int i = 0; i < Q; ++i) fb[(long)i * N + idx] = fout[i];
             }
+}
+
+void oracle_step(const double *fa, double *fb, const uint8_t *solid, int32_t nx, int32_t ny, int32_t nz,
+                 int32_t periodic, int32_t model, double tau, const double *force, double fx, double fy,
+                 double fz) {
+    step_bc(fa, fb, solid, nx, ny, nz, periodic, model, tau, force, fx, fy, fz, NULL);
+}
+
+/* n steps with open boundaries (type [N]: 0 none, 1 velocity inlet, 2 pressure outlet) */
+void oracle_run_bc(double *f, double *scratch, const uint8_t *solid, int32_t nx, int32_t ny, int32_t nz,
+                   int32_t periodic, int32_t model, double tau, const double *force, double fx, double fy,
+                   double fz, int32_t nsteps, const uint8_t *type, const double *u_in, double rho_out) {
+    bc_t bc = {type, {u_in[0], u_in[1], u_in[2]}, rho_out};
+    long N = (long)nx * ny * nz;
+    double *a = f, *b = scratch;
+    for (int s = 0; s < nsteps; ++s) {
+        step_bc(a, b, solid, nx, ny, nz, periodic, model, tau, force, fx, fy, fz, &bc);
+        double *t = a;
+        a = b;
+        b = t;
+    }
+    if (a != f) memcpy(f, a, sizeof(double) * (size_t)Q * (size_t)N);
 }
 
 /* n steps, ping-ponging between f (in/out) and a scratch array of the same size */
