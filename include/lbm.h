@@ -138,6 +138,7 @@ typedef struct lbm_sizes {
     size_t force_bytes;      /* per-node force field in tile order: n_tiles * 3 * 64 * sizeof(arith) */
     size_t adjoint_bytes;    /* one adjoint lattice: state_bytes (FP64, FP32), 0 for FP16 */
     size_t grad_force_bytes; /* force gradient, FP64: n_tiles * 3 * 64 * 8 */
+    size_t bc_bytes;         /* open-boundary masks: n_tiles * 2 * 8 */
     size_t dense_nodes;      /* nx * ny * nz of the padded box */
 } lbm_sizes;
 
@@ -174,6 +175,22 @@ int lbm_init(lbm_ctx *ctx, double rho0, double ux, double uy, double uz);
  * then on; gx, gy, gz are ignored. */
 int lbm_set_force(lbm_ctx *ctx, double gx, double gy, double gz, const double *g_dense_dev,
                   void *g_tile_buf);
+
+/* Open boundaries (the paper's Zou-He velocity inlet and constant-pressure
+ * outlet, Section 2.2) on faces normal to x.
+ *   type_host  host [nz][ny][nx] bytes over the padded box: 0 none,
+ *              1 velocity inlet (the domain lies at +x: the populations with
+ *              c_x = +1 are rebuilt so that the node's velocity is u),
+ *              2 pressure outlet (the domain lies at -x: the populations with
+ *              c_x = -1 are rebuilt so that its density is rho_out and its
+ *              tangential velocity 0); NULL removes all open boundaries
+ *   bc_tile_buf  device buffer of bc_bytes (caller-owned, must outlive its use)
+ * The rebuild follows the gather (which bounces back at the missing
+ * upstream nodes) and precedes the collision; with a body force it targets the
+ * momentum rho u - F/2 so that the collision's velocity is the prescribed
+ * one.  Flagged nodes must be fluid (else LBM_E_INVAL).  Synchronises. */
+int lbm_set_boundaries(lbm_ctx *ctx, const uint8_t *type_host, double ux, double uy, double uz, double rho_out,
+                       void *bc_tile_buf);
 
 /* n fused collide-and-stream steps on the context's stream, alternating the
  * two lattices (Alg. 2).  Asynchronous. */

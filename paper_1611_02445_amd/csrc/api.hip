@@ -29,6 +29,7 @@ struct lbm_ctx {
     Phys P;
     size_t state_bytes;
     int device;
+    std::vector<int32_t> corner;  // [n_tiles][3] tile corners in device order (host copy)
 };
 
 namespace {
@@ -137,6 +138,7 @@ extern "C" int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *para
     // FP16 storage has no adjoint
     out->adjoint_bytes = params->storage == LBM_F16S ? 0 : out->state_bytes;
     out->grad_force_bytes = n * 3 * TILE * sizeof(double);
+    out->bc_bytes = n * 2 * sizeof(uint64_t);
     out->dense_nodes = (size_t)tiles->nx * (size_t)tiles->ny * (size_t)tiles->nz;
     return LBM_OK;
 }
@@ -195,6 +197,7 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
         inv.assign((size_t)n, 0);
         for (int64_t d = 0; d < n; ++d) inv[perm[d]] = (int32_t)d;
         std::vector<unsigned char> host(lay.total, 0);
+        c->corner.assign((size_t)n * 3, 0);
         TileRec *rec = reinterpret_cast<TileRec *>(host.data() + lay.rec_off);
         uint64_t *nbm = reinterpret_cast<uint64_t *>(host.data() + lay.nbm_off);
         uint32_t *nbb32 = reinterpret_cast<uint32_t *>(host.data() + lay.nbb32_off);
@@ -211,6 +214,7 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
                 rec[d].base = (uint64_t)d * Q * TILE;
             }
             for (int a = 0; a < 3; ++a) xyz[4 * d + a] = tiles->tile_xyz[3 * i + a];
+            for (int a = 0; a < 3; ++a) c->corner[3 * d + a] = tiles->tile_xyz[3 * i + a];
             xyz[4 * d + 3] = 0;
         }
         // neighbourhood rows (needs every tile's record first)
@@ -306,6 +310,59 @@ extern "C" int lbm_set_force(lbm_ctx *c, double gx, double gy, double gz, const 
     if (e != hipSuccess) return hip_fail(e, "lbm_set_force");
     c->P.field = g_tile_buf;
     c->P.F[0] = c->P.F[1] = c->P.F[2] = 0.0;
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_boundaries(lbm_ctx *c, const uint8_t *type_host, double ux, double uy, double uz,
+                                  double rho_out, void *bc_tile_buf) {
+    CHECK_CTX(c);
+    if (!type_host) {
+        c->P.bc = nullptr;
+        return LBM_OK;
+    }
+    if (!std::isfinite(ux) || !std::isfinite(uy) || !std::isfinite(uz) || !std::isfinite(rho_out) || !(rho_out > 0))
+        return fail(LBM_E_INVAL, "lbm_set_boundaries: non-finite velocity or non-positive density");
+    if (!(ux < 1.0)) return fail(LBM_E_INVAL, "lbm_set_boundaries: inlet velocity u_x must be below 1");
+    if (c->n_tiles > 0 && !bc_tile_buf) return fail(LBM_E_INVAL, "lbm_set_boundaries: NULL tile buffer");
+    const size_t nx = (size_t)c->nx, ny = (size_t)c->ny, nz = (size_t)c->nz;
+    // every flagged node must be a fluid node of a kept tile
+    size_t flagged = 0;
+    for (size_t n = 0; n < nx * ny * nz; ++n) {
+        if (type_host[n] > 2) return fail(LBM_E_INVAL, "lbm_set_boundaries: node type %d is not 0, 1 or 2", type_host[n]);
+        flagged += type_host[n] != 0;
+    }
+    std::vector<uint64_t> masks((size_t)c->n_tiles * 2, 0);
+    size_t found = 0;
+    for (int64_t d = 0; d < c->n_tiles; ++d) {
+        const size_t x0 = (size_t)c->corner[3 * d], y0 = (size_t)c->corner[3 * d + 1], z0 = (size_t)c->corner[3 * d + 2];
+        for (int lane = 0; lane < TILE; ++lane) {
+            const size_t x = x0 + (lane & 3), y = y0 + ((lane >> 2) & 3), z = z0 + (lane >> 4);
+            const uint8_t t = type_host[x + nx * (y + ny * z)];
+            if (t == 1) masks[2 * d] |= 1ull << lane;
+            if (t == 2) masks[2 * d + 1] |= 1ull << lane;
+            found += t != 0;
+        }
+    }
+    if (found != flagged) return fail(LBM_E_INVAL, "lbm_set_boundaries: %zu flagged nodes lie in dropped tiles", flagged - found);
+    // ... and fluid inside its tile
+    std::vector<TileRec> rec((size_t)c->n_tiles);
+    hipError_t e = hipMemcpyAsync(rec.data(), c->L.tb.rec, rec.size() * sizeof(TileRec), hipMemcpyDeviceToHost,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_set_boundaries: reading tile masks");
+    for (int64_t d = 0; d < c->n_tiles; ++d)
+        if ((masks[2 * d] | masks[2 * d + 1]) & ~rec[d].mask)
+            return fail(LBM_E_INVAL, "lbm_set_boundaries: a flagged node is solid");
+    if (c->n_tiles > 0) {
+        e = hipMemcpyAsync(bc_tile_buf, masks.data(), masks.size() * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(e, "lbm_set_boundaries: upload");
+    }
+    c->P.bc = reinterpret_cast<const uint64_t *>(bc_tile_buf);
+    c->P.bc_u[0] = ux;
+    c->P.bc_u[1] = uy;
+    c->P.bc_u[2] = uz;
+    c->P.bc_rho = rho_out;
     return LBM_OK;
 }
 
@@ -412,6 +469,7 @@ static int adjoint_supported(lbm_ctx *c) {
     if (c->params.storage == LBM_F16S) return fail(LBM_E_UNSUPPORTED, "adjoint: built for FP64 and FP32 storage only");
     if (c->params.model != LBM_QUASI_COMPRESSIBLE)
         return fail(LBM_E_UNSUPPORTED, "adjoint: built for the quasi-compressible LBGK model only");
+    if (c->P.bc) return fail(LBM_E_UNSUPPORTED, "adjoint: not built for open boundaries");
     return LBM_OK;
 }
 

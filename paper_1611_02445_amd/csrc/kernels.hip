@@ -523,6 +523,64 @@ __device__ __forceinline__ void collide_mrt(T (&d)[Q], T rho_base, T omega, T Fx
     }
 }
 
+// ---------------------------------------------------------------------------
+// open boundaries (the paper's Zou-He velocity inlet and constant-pressure
+// outlet) on faces normal to x.  After the gather, an inlet node rebuilds its
+// populations with c_x = +1, an outlet node those with c_x = -1, each from its
+// opposite:  f_i = f_opp(i) + 6 w_i (c_i . J) - c_iy N_y - c_iz N_z,
+// N_t = 1/2 sum_{c_x = 0} c_t f - J_t / 3 (tangential-momentum correction),
+// with J = rho u - F/2 (inlet: rho from the known populations and u_x) or
+// J_x from the outlet density and J_t = -F_t/2.  On shifted values the
+// rebuild is unchanged (opposite directions have equal weights); only the
+// density sums add rho_base times the weights of their sets (2/3 for
+// c_x = 0, 1/6 for either normal set).
+// ---------------------------------------------------------------------------
+template <typename T, int INC>
+__device__ __forceinline__ void open_boundary(T (&d)[Q], const Phys &P, int t, T Fx, T Fy, T Fz) {
+    const uint64_t in_m = P.bc[2 * (size_t)t], out_m = P.bc[2 * (size_t)t + 1];
+    if (!(in_m | out_m)) return;  // no boundary node in this tile
+    const bool is_in = lane_on(in_m), is_out = lane_on(out_m);
+    if (!(is_in || is_out)) return;
+    const T rb = T(P.rho_base);
+    T s_tan = 0, s_neg = 0, s_pos = 0, ty = 0, tz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (CX[i] == 0) {
+            s_tan += d[i];
+            if (CY[i]) ty += CY[i] > 0 ? d[i] : -d[i];
+            if (CZ[i]) tz += CZ[i] > 0 ? d[i] : -d[i];
+        } else if (CX[i] < 0) {
+            s_neg += d[i];
+        } else {
+            s_pos += d[i];
+        }
+    }
+    s_tan += rb * T(2.0 / 3.0);
+    s_neg += rb * T(1.0 / 6.0);
+    s_pos += rb * T(1.0 / 6.0);
+    T Jx, Jy, Jz;
+    if (is_in) {
+        const T ux = T(P.bc_u[0]), uy = T(P.bc_u[1]), uz = T(P.bc_u[2]);
+        const T r = INC ? T(1) : (s_tan + T(2) * s_neg - T(0.5) * Fx) / (T(1) - ux);
+        Jx = r * ux - T(0.5) * Fx;
+        Jy = r * uy - T(0.5) * Fy;
+        Jz = r * uz - T(0.5) * Fz;
+    } else {
+        Jx = s_tan + T(2) * s_pos - T(P.bc_rho);
+        Jy = -T(0.5) * Fy;
+        Jz = -T(0.5) * Fz;
+    }
+    const T Ny = T(0.5) * ty - Jy * T(1.0 / 3.0), Nz = T(0.5) * tz - Jz * T(1.0 / 3.0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (CX[i] == 0) continue;
+        if ((CX[i] > 0 && is_in) || (CX[i] < 0 && is_out)) {
+            const T cJ = T(CX[i]) * Jx + T(CY[i]) * Jy + T(CZ[i]) * Jz;
+            d[i] = d[opposite(i)] + T(6.0 * weight(i)) * cJ - T(CY[i]) * Ny - T(CZ[i]) * Nz;
+        }
+    }
+}
+
 // the collision of a model: LBGK (0, 1) or multiple relaxation times (2, 3)
 template <typename T, int MODEL>
 __device__ __forceinline__ void collide_model(T (&d)[Q], T rho_base, T omega, T kg, T Fx, T Fy, T Fz) {
@@ -587,6 +645,7 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
         for (int i = 0; i < Q; ++i) d[i] = C::dec(raw[i], a.P.inv_scale);
         T Fx, Fy, Fz;
         load_force<T>(a.P, t, lane, Fx, Fy, Fz);
+        if (a.P.bc) open_boundary<T, (MODEL & 1)>(d, a.P, t, Fx, Fy, Fz);
         collide_model<T, MODEL>(d, T(a.P.rho_base), T(a.P.omega), T(a.P.kg), Fx, Fy, Fz);
     }
     if constexpr (ST == LBM_F16S) {

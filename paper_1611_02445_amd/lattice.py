@@ -103,6 +103,7 @@ class Lattice:
         self.tables = buf(sz.table_bytes)
         self.scratch = buf(sz.scratch_bytes)
         self.force_buf = None
+        self.bc_buf = None
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
         call("lbm_create", self.tiling._ptr, ctypes.byref(self.params), _vp(self.state_a), _vp(self.state_b),
@@ -158,6 +159,21 @@ class Lattice:
         else:
             gx, gy, gz = map(float, g)
             call("lbm_set_force", self.ctx, gx, gy, gz, None, None)
+
+    def set_boundaries(self, types, u_in=(0.0, 0.0, 0.0), rho_out=1.0):
+        """Open boundaries on faces normal to x: types is a uint8 array over the
+        padded box [nz, ny, nx] (0 none, 1 velocity inlet u_in, 2 pressure
+        outlet rho_out), or None to remove them."""
+        if types is None:
+            call("lbm_set_boundaries", self.ctx, None, 0.0, 0.0, 0.0, 1.0, None)
+            return
+        t = np.ascontiguousarray(types, dtype=np.uint8)
+        if t.shape != self.dense_shape:
+            raise ValueError(f"boundary types must have shape {self.dense_shape}")
+        if self.bc_buf is None:
+            self.bc_buf = self.torch.empty(max(self.sizes.bc_bytes, 1), dtype=self.torch.uint8, device=self.device)
+        call("lbm_set_boundaries", self.ctx, t.ctypes.data_as(ctypes.c_void_p), *map(float, u_in), float(rho_out),
+             _vp(self.bc_buf))
 
     def step(self, n=1):
         call("lbm_step", self.ctx, int(n))

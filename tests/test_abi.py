@@ -76,3 +76,10 @@ def test_null_arguments():
     assert _abi.lib().lbm_build_tiles(None, 4, 4, 4, 0, None) == -1
     assert _abi.lib().lbm_step(None, 1) == -1
     assert _abi.lib().lbm_macroscopic(None, None, None, None) == -1
+
+
+def test_boundary_buffer_size():
+    t = Tiling(np.zeros((8, 12, 16), np.uint8), 7)
+    sz = _abi.Sizes()
+    _abi.call("lbm_required_bytes", t._ptr, ctypes.byref(_params()), ctypes.byref(sz))
+    assert sz.bc_bytes == 24 * 2 * 8

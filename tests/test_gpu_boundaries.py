@@ -1,0 +1,112 @@
+"""Open boundaries (Zou-He velocity inlet, constant-pressure outlet) on the
+GPU against the oracle: channels and a porous plug, both equilibria and both
+operators, FP64 at the parity bar and the reduced storages at their bounds."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1611_02445_amd import inputs as I
+
+from helpers import log, new_lattice, padded, perturbed_state, rel_err_f
+
+pytestmark = pytest.mark.gpu
+
+
+def _open_channel(nx, H, nz, plug=None):
+    """Walls at y = 0 and y = H + 1, periodic in z, inlet plane x = 0 and
+    outlet plane x = nx - 1 on the fluid rows (nx a multiple of 4: no
+    padding in x).  plug: optional solid bitmap of the same shape or'd in."""
+    solid = np.zeros((nz, H + 2, nx), np.uint8)
+    solid[:, 0, :] = 1
+    solid[:, -1, :] = 1
+    if plug is not None:
+        solid |= plug
+    bt = np.zeros_like(solid)
+    bt[:, :, 0] = np.where(solid[:, :, 0] == 0, 1, 0)
+    bt[:, :, -1] = np.where(solid[:, :, -1] == 0, 2, 0)
+    return solid, bt
+
+
+def _compare(solid, bt, periodic, tau, steps, u_in, rho_out, model="qc", storage="f64", g=(0.0, 0.0, 0.0),
+             seed=None):
+    import torch
+    sp = padded(solid, periodic)
+    btp = np.zeros_like(sp)
+    btp[:bt.shape[0], :bt.shape[1], :bt.shape[2]] = bt
+    lat = new_lattice(solid, tau, periodic, model=model, storage=storage)
+    lat.init()
+    f0 = O.init(sp, model=O.MODELS[model])
+    if seed is not None:
+        f0 = perturbed_state(sp, seed)
+        lat.set_state(torch.from_numpy(f0))
+    lat.set_force(g)
+    lat.set_boundaries(btp, u_in=u_in, rho_out=rho_out)
+    lat.step(steps)
+    got = lat.get_state().cpu().numpy()
+    ref = O.run_bc(f0, sp, tau, steps, btp, u_in=u_in, rho_out=rho_out, force=np.array(g), periodic=periodic,
+                   model=O.MODELS[model])
+    return lat, sp, btp, got, ref
+
+
+@pytest.mark.parametrize("model", ["qc", "inc", "mrt-qc"])
+def test_open_channel_matches_oracle(model):
+    solid, bt = _open_channel(32, 10, 8)
+    log(f"[case] open channel model={model}")
+    lat, sp, _, got, ref = _compare(solid, bt, 4, 0.8, 300, (0.02, 0.001, -0.002), 1.0, model=model)
+    err = rel_err_f(got, ref, sp)
+    log(f"   f rel err {err:.3e}")
+    assert err <= 1e-12
+
+
+def test_porous_plug_with_force_and_perturbation():
+    plug, _ = I.sphere_pack((8, 14, 24), 0.6, 1.5, 3.0, seed=17, periodic=False)
+    plug[:, :, :4] = 0  # keep the inlet and outlet planes open
+    plug[:, :, -4:] = 0
+    solid, bt = _open_channel(24, 12, 8, plug=plug)
+    log("[case] porous plug")
+    lat, sp, btp, got, ref = _compare(solid, bt, 4, 0.7, 200, (0.01, 0.0, 0.0), 0.998, g=(2e-6, 1e-6, 0.0),
+                                      seed=11)
+    err = rel_err_f(got, ref, sp)
+    log(f"   f rel err {err:.3e}")
+    assert err <= 1e-12
+    # the inlet nodes carry the prescribed velocity, the outlet nodes the density
+    rho, u, _ = lat.macroscopic()
+    rho, u = rho.cpu().numpy(), u.cpu().numpy()
+    fin = btp == 1
+    fout = btp == 2
+    assert fin.sum() > 0 and fout.sum() > 0
+    assert np.abs(u[0][fin] - 0.01).max() <= 1e-12
+    assert np.abs(rho[fout] - 0.998).max() <= 1e-12
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_open_channel_reduced_storage(storage):
+    solid, bt = _open_channel(32, 10, 8)
+    steps = 200
+    lat, sp, _, got, ref = _compare(solid, bt, 4, 0.8, steps, (0.02, 0.0, 0.0), 1.0, storage=storage)
+    fl = sp == 0
+    _, w, _ = O.lattice()
+    d = np.abs(ref - w[:, None, None, None])[:, fl].max()
+    err = np.abs(got[:, fl] - ref[:, fl]).max()
+    bound = steps * 2.0 ** -24 * d * 8 if storage == "f32" else steps * 2.0 ** -10 * d
+    log(f"[case] open channel {storage}: max |df| {err:.3e} bound {bound:.3e}")
+    assert err <= bound
+
+
+def test_boundaries_validated_and_removable():
+    from paper_1611_02445_amd._abi import LbmError
+    solid, bt = _open_channel(16, 6, 4)
+    lat = new_lattice(solid, 0.8, 4)
+    bad = bt.copy()
+    bad[0, 0, 0] = 1  # a wall node
+    with pytest.raises(LbmError):
+        lat.set_boundaries(bad, u_in=(0.01, 0, 0))
+    with pytest.raises(LbmError):
+        lat.set_boundaries(bt * 3)
+    lat.set_boundaries(bt, u_in=(0.01, 0, 0))
+    lat.set_boundaries(None)
+    lat.init()
+    f0 = lat.get_state()
+    lat.step(20)
+    # rest, walls only: nothing moves beyond the rounding of the weights' sum
+    assert (lat.get_state() - f0).abs().max().item() <= 1e-15
