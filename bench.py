@@ -259,6 +259,51 @@ def time_pack1024(args, torch):
     return out
 
 
+def _time_calib_kind(lat, kind, torch, launches=200, warmup=10):
+    a, b = lat.new_state(), lat.new_state()
+    a.copy_(lat.current_state())
+    for _ in range(warmup):
+        lat.calib_step(kind, a, b)
+        a, b = b, a
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(lat.stream)
+    for _ in range(launches):
+        lat.calib_step(kind, a, b)
+        a, b = b, a
+    ev1.record(lat.stream)
+    torch.cuda.synchronize()
+    del a, b
+    return ev0.elapsed_time(ev1) / launches
+
+
+def sweep_layouts(args, torch):
+    """The paper's intra-tile layout study (Section 3.3, Eqs. 11-13; Table 5):
+    the propagation-only kernel with the per-direction slot maps XYZ, XYZ +
+    zigzagNE, XYZ + YXZ and all three, against the read/write-only kernel, on
+    fully fluid boxes with bounce-back walls (the paper's 100^3 cavity, 25^3
+    tiles, and a 256^3 one that no cache holds)."""
+    from paper_1611_02445_amd.lattice import Lattice
+    names = {1: "rw only", 3: "XYZ", 4: "XYZ + zigzagNE", 5: "XYZ + YXZ", 6: "all three"}
+    rows = []
+    for n in (100, 256):
+        for st in ("f64", "f32"):
+            lat = Lattice(np.zeros((n, n, n), np.uint8), 0.7, periodic=0, storage=st, tiles_per_wg=args.tpw,
+                          tile_order=args.order)
+            lat.init()
+            for kind in (3, 4, 5, 6, 1):
+                ms = _time_calib_kind(lat, kind, torch, launches=max(10, min(200, args.steps)),
+                                      warmup=max(2, min(10, args.warmup)))
+                mf = lat.n_fluid / (ms / 1e3) / 1e6
+                rows.append({"box": n, "storage": st, "layout": names[kind], "kind": kind, "us": round(ms * 1e3, 2),
+                             "MFLUPS": round(mf, 1),
+                             "bw_util": round(mf * 1e6 * BYTES_PER_UPDATE[st] / (HBM_PEAK_GBS * 1e9), 4)})
+                log(f"[bench] layouts {n}^3 {st} {names[kind]}: {ms * 1e3:.1f} us, {mf:.0f} MFLUPS, "
+                    f"{rows[-1]['bw_util']:.3f}")
+            del lat
+            torch.cuda.empty_cache()
+    return rows
+
+
 def sweep_sphere_arrays(args, torch):
     """Random sphere arrays of diameter 40 in a 192^3 periodic box at the nine
     porosities of the paper's sparse-geometry table (Section 4.6, Table 6):
@@ -266,12 +311,21 @@ def sweep_sphere_arrays(args, torch):
     from paper_1611_02445_amd import inputs
     from paper_1611_02445_amd.lattice import Lattice
     rows = []
-    for p in (0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2, 0.1):
-        solid, _ = inputs.sphere_pack((192, 192, 192), p, 20.0, 20.0, seed=11)
+    for p in (1.0, 0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2, 0.1):
+        if p == 1.0:  # the dense normaliser: a fully fluid box with bounce-back walls
+            solid = np.zeros((192, 192, 192), np.uint8)
+        else:
+            solid, _ = inputs.sphere_pack((192, 192, 192), p, 20.0, 20.0, seed=11)
         row = {"porosity": p}
+        per = 0 if p == 1.0 else 7
+        lat = Lattice(solid, 0.7, periodic=per, storage="f64")
+        lat.init()
+        for kind, name in ((1, "rw"), (2, "prop")):
+            row[f"MFLUPS_f64_{name}"] = round(lat.n_fluid / (_time_calib_kind(lat, kind, torch, 500) / 1e3) / 1e6, 1)
+        del lat
         for st in ("f64", "f32"):
             for model in ("inc", "qc", "mrt-inc", "mrt-qc"):
-                lat = Lattice(solid, 0.7, periodic=7, storage=st, model=model)
+                lat = Lattice(solid, 0.7, periodic=per, storage=st, model=model)
                 lat.init()
                 lat.set_force((1e-6, 0.0, 0.0))
                 lat.step(args.warmup)
@@ -287,7 +341,20 @@ def sweep_sphere_arrays(args, torch):
         log(f"[bench] spheres192 porosity {p}: eta_t {row['eta_t']} f64 qc {row['MFLUPS_f64_qc']} "
             f"f32 qc {row['MFLUPS_f32_qc']} MFLUPS")
         rows.append(row)
-    return rows
+    # the paper's Fig. 12: each kernel's MFLUPS over its dense-box MFLUPS
+    # against tile utilisation, and the slope alpha of the line through
+    # (1, 1) that fits it: normalised ~ 1 - alpha (1 - eta_t)
+    dense, sparse = rows[0], rows[1:]
+    fits = {}
+    for key in dense:
+        if not key.startswith("MFLUPS_"):
+            continue
+        x = np.array([1.0 - r["eta_t"] for r in sparse])
+        y = np.array([1.0 - r[key] / dense[key] for r in sparse])
+        for r in sparse:
+            r["norm_" + key[7:]] = round(r[key] / dense[key], 4)
+        fits[key[7:]] = round(float((x * y).sum() / (x * x).sum()), 4)
+    return {"rows": rows, "alpha": fits}
 
 
 def sweep_channels(args, torch):
@@ -386,6 +453,8 @@ def main():
                     help="also run the 1024x512x512 FP32 forward + adjoint workload (about 2 minutes)")
     ap.add_argument("--sweep192", action="store_true",
                     help="also time the step on 192^3 random sphere arrays at porosities 0.9..0.1")
+    ap.add_argument("--layouts", action="store_true",
+                    help="also time the paper's intra-tile layout study (propagation-only kernel, Table 5)")
     ap.add_argument("--sweep-channels", action="store_true",
                     help="also time the propagation-only kernel on rectangular channels (the paper's Eqs. 17-19 study)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -551,6 +620,9 @@ def main():
         torch.cuda.empty_cache()
     if args.sweep192:
         result["sphere_arrays_192"] = sweep_sphere_arrays(args, torch)
+        torch.cuda.empty_cache()
+    if args.layouts:
+        result["layouts"] = sweep_layouts(args, torch)
         torch.cuda.empty_cache()
     if args.sweep_channels:
         result["channels_propagation"] = sweep_channels(args, torch)

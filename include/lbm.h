@@ -280,6 +280,16 @@ int lbm_adjoint_set(lbm_ctx *ctx, const double *dense_dev, void *adj);
  * kernels, Section 4.1): same tiles and launch shape as a step, kind 1 reads
  * and writes each node's own 19 values, kind 2 performs the full gather and
  * bounce-back and stores the gathered values without collision.
+ * Kinds 3-6 are the propagation-only kernel of the paper's intra-tile layout
+ * study (Section 3.3, Eqs. 11-13, Table 5): each direction's 64-slot block
+ * orders the tile's nodes by the XYZ map (x + 4y + 16z), the YXZ map
+ * (y + 4x + 16z) or the zigzagNE map; kind 3 uses XYZ for every direction,
+ * kind 4 adds zigzagNE for NE and SE, kind 5 YXZ for E, W, ET, EB, NW, SW,
+ * WT and WB, kind 6 both.  src and dst are read and written in that layout
+ * (not the library's state layout, except for kind 3, whose bytes equal it).
+ * They need every kept tile entirely fluid (else LBM_E_UNSUPPORTED), where
+ * the layouts occupy the same bytes as a state lattice.
+ * src != dst, both state lattices of this context (else LBM_E_INVAL).
  * ------------------------------------------------------------------------ */
 int lbm_calib_step(lbm_ctx *ctx, int32_t kind, const void *src, void *dst);
 

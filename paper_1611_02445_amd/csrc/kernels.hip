@@ -690,6 +690,64 @@ __global__ __launch_bounds__(512) void k_calib(KArgs a) {
     store_tile<S, RN, OffT, true>(a.dst, me, own, fl, lane, [&](int i) { return v[i]; });
 }
 
+// The paper's intra-tile layout study (Section 3.3, Eqs. 11-13; Table 5):
+// the propagation-only kernel on the plain layout, with the slot of node
+// (x, y, z) in direction i's 64-slot block given per direction by
+//   XYZ      x + 4y + 16z                                  (default)
+//   YXZ      y + 4x + 16z        for E, W, ET, EB, NW, SW, WT, WB  (LS bit 0)
+//   zigzagNE 2(x + 3y + [x = 3](3 - y)·4) + (z & 1) + 16(z & 2)
+//                                for NE, SE                        (LS bit 1)
+// Only defined on tiles that are entirely fluid (the host checks), where the
+// plain and the runs layouts occupy the same bytes.
+__device__ __forceinline__ int layout_slot(int ls, int i, int x, int y, int z) {
+    const bool yxz = (ls & 1) && (i == 1 || i == 3 || i == 8 || i == 9 || i == 11 || i == 12 || i == 13 || i == 14);
+    const bool zig = (ls & 2) && (i == 7 || i == 10);
+    if (yxz) return y + 4 * x + 16 * z;
+    if (zig) return 2 * (x + 3 * y + ((x + 1) & 4) * (3 - y)) + (z & 1) + 16 * (z & 2);
+    return x + 4 * y + 16 * z;
+}
+
+template <int LS, int I, typename S, typename OffT>
+__device__ __forceinline__ S gather_layout(const Nbhd<OffT> &h, const char *base, const Self<false, OffT> &me, int x,
+                                           int y, int z, int lane) {
+    if constexpr (I == 0) {
+        return load_elem<OffT, S>(base, me.base + (OffT)layout_slot(LS, 0, x, y, z));
+    } else {
+        constexpr int SX = -CX[I], SY = -CY[I], SZ = -CZ[I], OP = opposite(I);
+        const uint64_t ok = source_fluid<SX, SY, SZ>(h);
+        const int xs = (x + SX) & 3, ys = (y + SY) & 3, zs = (z + SZ) & 3;
+        // source_elem addresses slot xs + 4ys + 16zs of the source tile's block
+        const OffT e = source_elem<SX, SY, SZ, I, false, OffT>(h, lane) - (OffT)(xs + 4 * ys + 16 * zs) +
+                       (OffT)layout_slot(LS, I, xs, ys, zs);
+        const OffT bb = me.base + (OffT)(OP * TILE + layout_slot(LS, OP, x, y, z));
+        return load_elem<OffT, S>(base, lane_on(ok) ? e : bb);
+    }
+}
+
+template <int LS, typename S, typename OffT, int... Is>
+__device__ __forceinline__ void gather_layout_all(S (&v)[Q], const Nbhd<OffT> &h, const char *base,
+                                                  const Self<false, OffT> &me, int x, int y, int z, int lane,
+                                                  std::integer_sequence<int, Is...>) {
+    ((v[Is] = gather_layout<LS, Is, S, OffT>(h, base, me, x, y, z, lane), __builtin_amdgcn_sched_barrier(0)), ...);
+}
+
+template <typename S, int LS, typename OffT>
+__global__ __launch_bounds__(512) void k_calib_layout(KArgs a) {
+    const int t = wave_tile(a.wpb, a.nblocks);
+    if (t >= a.n_tiles) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const int x = lane & 3, y = (lane >> 2) & 3, z = lane >> 4;
+    const TileRec rec = a.tb.rec[t];
+    const Self<false, OffT> me(rec, lane);
+    Nbhd<OffT> h;
+    load_nbhd(h, a.tb, t);
+    S v[Q];
+    gather_layout_all<LS, S, OffT>(v, h, a.src, me, x, y, z, lane, std::make_integer_sequence<int, Q>{});
+    S *out = reinterpret_cast<S *>(a.dst);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) store_stream(out + (me.base + (OffT)(i * TILE + layout_slot(LS, i, x, y, z))), v[i]);
+}
+
 // ---------------------------------------------------------------------------
 // initial state: feq(rho0, u0) at every fluid node of both lattices, 0 in the
 // padding
@@ -1155,10 +1213,37 @@ static hipError_t calib_t(const Launch &L, const KArgs &a) {
     return hipGetLastError();
 }
 
+template <typename S, int LS>
+static hipError_t calib_layout_t(const Launch &L, const KArgs &a) {
+    if (L.off32)
+        hipLaunchKernelGGL((k_calib_layout<S, LS, uint32_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
+    else
+        hipLaunchKernelGGL((k_calib_layout<S, LS, uint64_t>), dim3(L.grid), block_of(L), 0, L.stream, a);
+    return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t calib_layout_s(const Launch &L, const KArgs &a, int ls) {
+    switch (ls) {
+    case 0: return calib_layout_t<S, 0>(L, a);
+    case 1: return calib_layout_t<S, 1>(L, a);
+    case 2: return calib_layout_t<S, 2>(L, a);
+    default: return calib_layout_t<S, 3>(L, a);
+    }
+}
+
 hipError_t launch_calib(const Launch &L, int kind, int storage, const void *src, void *dst) {
     if (L.n_tiles == 0) return hipSuccess;
     Phys P{};
     const KArgs a = make_args(L, P, src, dst);
+    if (kind >= 3) {
+        // kinds 3..6: layout sets XYZ, XYZ+zigzagNE, XYZ+YXZ, all three
+        static constexpr int LS[4] = {0, 2, 1, 3};
+        const int ls = LS[kind - 3];
+        if (storage == LBM_F64) return calib_layout_s<double>(L, a, ls);
+        if (storage == LBM_F32) return calib_layout_s<float>(L, a, ls);
+        return calib_layout_s<_Float16>(L, a, ls);
+    }
     if (storage == LBM_F64) return kind == 1 ? calib_t<LBM_F64, 1>(L, a) : calib_t<LBM_F64, 2>(L, a);
     if (storage == LBM_F32) return kind == 1 ? calib_t<LBM_F32, 1>(L, a) : calib_t<LBM_F32, 2>(L, a);
     return kind == 1 ? calib_t<LBM_F16S, 1>(L, a) : calib_t<LBM_F16S, 2>(L, a);

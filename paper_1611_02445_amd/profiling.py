@@ -4,13 +4,18 @@
     python -m paper_1611_02445_amd.profiling counters <fetch_dir> <write_dir> <copy_fetch_dir> \
         <copy_write_dir> <copy_bytes> <kernel_substring> <grid_size|any> <out.json> <command...>
 
+    python -m paper_1611_02445_amd.profiling table <out.txt> <command> <copy_fetch_dir> <copy_write_dir> \
+        <copy_bytes> <pmc_dir>... -- <label>=<kernel_substring>@<grid_size|any> ...
+
 ``trace`` turns a ``rocprofv3 --kernel-trace --stats -f csv`` directory into a
 per-kernel table (calls, average / min / max duration).  ``counters`` turns
 two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of the workload plus the
 same two counters read on a plain device copy of known size (copy_bytes read
 and copy_bytes written) into HBM bytes per launch: each counter is scaled by
 copy_bytes / (the bytes that counter reported for the copy), which calibrates
-what the counter actually counts on this GPU.
+what the counter actually counts on this GPU.  ``table`` lists the
+per-dispatch average of every counter of some ``--pmc`` runs for chosen
+kernels.
 """
 import csv
 import glob
@@ -108,6 +113,39 @@ def counters_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, k
     }
 
 
+def counters_table(pmc_dirs, rows, command, cfetch_dir, cwrite_dir, copy_bytes):
+    """Per-dispatch averages of every counter found in the given --pmc runs,
+    one line per (label, kernel substring, grid size) row, plus the HBM bytes
+    read and written per dispatch (FETCH_SIZE and WRITE_SIZE scaled by the
+    copy calibration, as in counters_summary)."""
+    names = []
+    for d in pmc_dirs:
+        with open(_find(d, "*counter_collection.csv")) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] not in names:
+                    names.append(r["Counter_Name"])
+    fs = copy_bytes / (counter_per_dispatch(cfetch_dir, "FETCH_SIZE", "copyBuffer")[0] * 1024.0)
+    ws = copy_bytes / (counter_per_dispatch(cwrite_dir, "WRITE_SIZE", "copyBuffer")[0] * 1024.0)
+    out = [f"# rocprofv3 counters per dispatch: {command}",
+           f"# HBM MB = FETCH_SIZE (WRITE_SIZE) KiB x 1024 x {fs:.4f} ({ws:.4f}) / 1e6: the scale makes the counter "
+           f"read back a {copy_bytes / 2**30:g} GiB device copy's bytes", "",
+           f"{'row':<28}{'HBM_read_MB':>14}{'HBM_write_MB':>14}" + "".join(f"{n:>22}" for n in names)]
+    for label, sub, grid in rows:
+        vals = {}
+        for n in names:
+            for d in pmc_dirs:
+                try:
+                    vals[n] = counter_per_dispatch(d, n, sub, grid)[0]
+                    break
+                except ValueError:
+                    continue
+        rd = f"{vals['FETCH_SIZE'] * 1024.0 * fs / 1e6:14.1f}" if "FETCH_SIZE" in vals else f"{'-':>14}"
+        wr = f"{vals['WRITE_SIZE'] * 1024.0 * ws / 1e6:14.1f}" if "WRITE_SIZE" in vals else f"{'-':>14}"
+        out.append(f"{label:<28}{rd}{wr}" +
+                   "".join(f"{vals[n]:22.1f}" if n in vals else f"{'-':>22}" for n in names))
+    return "\n".join(out) + "\n"
+
+
 def main(argv):
     if len(argv) >= 4 and argv[1] == "trace":
         with open(argv[3], "w") as fh:
@@ -118,6 +156,17 @@ def main(argv):
         d = counters_summary(argv[2], argv[3], argv[4], argv[5], float(argv[6]), argv[7], " ".join(argv[10:]), grid)
         with open(argv[9], "w") as fh:
             json.dump(d, fh, indent=1)
+        return 0
+    if len(argv) >= 9 and argv[1] == "table" and "--" in argv:
+        cut = argv.index("--")
+        dirs = argv[7:cut]
+        rows = []
+        for spec in argv[cut + 1:]:
+            label, rest = spec.split("=", 1)
+            sub, grid = rest.rsplit("@", 1)
+            rows.append((label, sub, int(grid) if grid != "any" else None))
+        with open(argv[2], "w") as fh:
+            fh.write(counters_table(dirs, rows, argv[3], argv[4], argv[5], float(argv[6])))
         return 0
     print(__doc__, file=sys.stderr)
     return 2

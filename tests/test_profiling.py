@@ -58,3 +58,29 @@ def test_trace_table_groups_by_kernel_and_grid(tmp_path):
     t = P.trace_table(str(tmp_path / "t"))
     assert t[("k", 64)] == (2, 3.0, 2.0, 4.0)
     assert t[("k", 32)] == (1, 1.0, 1.0, 1.0)
+
+
+def test_counters_table_rows_and_calibrated_bytes(tmp_path):
+    f = ["Counter_Name", "Kernel_Name", "Grid_Size", "Counter_Value"]
+    _write_csv(str(tmp_path / "f" / "x_counter_collection.csv"),
+               [dict(Counter_Name="FETCH_SIZE", Kernel_Name="k_calib_layout<double, 0, u>", Grid_Size=64,
+                     Counter_Value=1000.0),
+                dict(Counter_Name="FETCH_SIZE", Kernel_Name="k_calib_layout<double, 2, u>", Grid_Size=64,
+                     Counter_Value=3000.0)], f)
+    _write_csv(str(tmp_path / "i" / "x_counter_collection.csv"),
+               [dict(Counter_Name="SQ_WAVES", Kernel_Name="k_calib_layout<double, 0, u>", Grid_Size=64,
+                     Counter_Value=7.0)], f)
+    _write_csv(str(tmp_path / "cf" / "x_counter_collection.csv"),
+               [dict(Counter_Name="FETCH_SIZE", Kernel_Name="copyBuffer", Grid_Size=1, Counter_Value=512.0)], f)
+    _write_csv(str(tmp_path / "cw" / "x_counter_collection.csv"),
+               [dict(Counter_Name="WRITE_SIZE", Kernel_Name="copyBuffer", Grid_Size=1, Counter_Value=1024.0)], f)
+    txt = P.counters_table([str(tmp_path / "f"), str(tmp_path / "i")],
+                           [("xyz", "k_calib_layout<double, 0,", 64), ("zig", "k_calib_layout<double, 2,", None)],
+                           "cmd", str(tmp_path / "cf"), str(tmp_path / "cw"), 1024.0 * 1024)
+    lines = txt.splitlines()
+    assert lines[0].endswith("cmd")
+    xyz = [ln for ln in lines if ln.startswith("xyz")][0].split()
+    zig = [ln for ln in lines if ln.startswith("zig")][0].split()
+    # HBM read MB = 1000 KiB x 1024 x 2 (fetch scale) / 1e6; no WRITE_SIZE run: "-"
+    assert xyz[1:] == ["2.0", "-", "1000.0", "7.0"]
+    assert zig[1:] == ["6.1", "-", "3000.0", "-"]
