@@ -22,7 +22,18 @@
  *     forcing is our reading: Guo, Zheng and Shi (2002) -- velocity shifted by
  *     F/2 and a second-order source term.
  *   - a discrete adjoint (reverse mode) of T steps for the loss
- *     "mean x-velocity over fluid nodes", storing every state.
+ *     "mean x-velocity over fluid nodes", storing every state,
+ *   - the multiple-relaxation-time operator the paper names for its LBMRT
+ *     kernels (Section 2.2; no matrix given): the D3Q19 moment basis and
+ *     relaxation rates of d'Humieres et al. (2002), both equilibria,
+ *   - the Zou-He velocity inlet and constant-pressure outlet the paper
+ *     names for its open boundaries (Section 2.2), on faces normal to x.
+ *
+ * Parity unpinned: the rates of the moments eps, q, pi and m (1.4, 1.2,
+ * 1.4, 1.98).  They act below the Navier-Stokes level, so no transport
+ * coefficient or closed form fixes them; they are the cited paper's values.
+ * The shear rate (1/tau) and the energy rate (1.19, through the bulk
+ * viscosity) are pinned.
  *
  * Arithmetic is plain C in double precision with the operations written in
  * the order of the formulas; build without FMA contraction.
