@@ -155,8 +155,10 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
         return fail(LBM_E_INVAL, "lbm_create: NULL device buffer");
     if (n > 0 && state_a == state_b) return fail(LBM_E_INVAL, "lbm_create: the two lattices must differ");
     // Validate every table entry the kernels will index with.
+    int64_t fluid = 0;
     for (int64_t i = 0; i < n; ++i) {
         if (tiles->fluid_mask[i] == 0) return fail(LBM_E_INVAL, "lbm_create: kept tile %lld has no fluid node", (long long)i);
+        fluid += __builtin_popcountll(tiles->fluid_mask[i]);
         for (int k = 0; k < 27; ++k) {
             const int32_t v = tiles->nbr[27 * i + k];
             if (v < -1 || v >= n) return fail(LBM_E_INVAL, "lbm_create: neighbour index %d out of range", v);
@@ -168,6 +170,11 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
             if (c < 0 || c % 4 || c + 4 > lim) return fail(LBM_E_INVAL, "lbm_create: tile corner out of the box");
         }
     }
+    // n_fluid normalises the adjoint loss and decides which measurement
+    // kernels may address a lattice as whole tiles: it must be the masks' count
+    if (fluid != tiles->n_fluid)
+        return fail(LBM_E_INVAL, "lbm_create: n_fluid %lld does not match the %lld fluid nodes of the masks",
+                    (long long)tiles->n_fluid, (long long)fluid);
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(LBM_E_NOMEM, "lbm_create: out of host memory");
     c->params = *params;

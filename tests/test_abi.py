@@ -83,3 +83,19 @@ def test_boundary_buffer_size():
     sz = _abi.Sizes()
     _abi.call("lbm_required_bytes", t._ptr, ctypes.byref(_params()), ctypes.byref(sz))
     assert sz.bc_bytes == 24 * 2 * 8
+
+
+def test_create_rejects_inconsistent_tiles():
+    """Table checks run before any device memory is touched: the dummy
+    buffer addresses below are never dereferenced."""
+    dummy = [ctypes.c_void_p(4096 * (k + 1)) for k in range(4)]
+    for field, value in (("n_fluid", 1), ("nbr", 99)):
+        t = Tiling(np.zeros((8, 8, 8), np.uint8), 7)
+        if field == "n_fluid":
+            t._ptr.contents.n_fluid += value
+        else:
+            t._ptr.contents.nbr[0] = value
+        ctx = ctypes.c_void_p()
+        rc = _abi.lib().lbm_create(t._ptr, ctypes.byref(_params()), *dummy, None, ctypes.byref(ctx))
+        assert rc == -1 and not ctx.value
+        assert field.encode() in _abi.lib().lbm_last_error() or b"neighbour" in _abi.lib().lbm_last_error()
