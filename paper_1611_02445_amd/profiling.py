@@ -117,7 +117,8 @@ def counters_table(pmc_dirs, rows, command, cfetch_dir, cwrite_dir, copy_bytes):
     """Per-dispatch averages of every counter found in the given --pmc runs,
     one line per (label, kernel substring, grid size) row, plus the HBM bytes
     read and written per dispatch (FETCH_SIZE and WRITE_SIZE scaled by the
-    copy calibration, as in counters_summary)."""
+    copy calibration, as in counters_summary) and the bytes read counted by
+    request size (32, 64 and 128-byte L2-to-memory read requests)."""
     names = []
     for d in pmc_dirs:
         with open(_find(d, "*counter_collection.csv")) as fh:
@@ -128,8 +129,11 @@ def counters_table(pmc_dirs, rows, command, cfetch_dir, cwrite_dir, copy_bytes):
     ws = copy_bytes / (counter_per_dispatch(cwrite_dir, "WRITE_SIZE", "copyBuffer")[0] * 1024.0)
     out = [f"# rocprofv3 counters per dispatch: {command}",
            f"# HBM MB = FETCH_SIZE (WRITE_SIZE) KiB x 1024 x {fs:.4f} ({ws:.4f}) / 1e6: the scale makes the counter "
-           f"read back a {copy_bytes / 2**30:g} GiB device copy's bytes", "",
-           f"{'row':<28}{'HBM_read_MB':>14}{'HBM_write_MB':>14}" + "".join(f"{n:>22}" for n in names)]
+           f"read back a {copy_bytes / 2**30:g} GiB device copy's bytes",
+           "# read_MB_by_size = (32 n32 + 64 n64 + 128 n128) / 1e6 from the TCC_EA0_RDREQ_{32B,64B,128B} "
+           "request counts, where a run holds them", "",
+           f"{'row':<28}{'HBM_read_MB':>14}{'HBM_write_MB':>14}{'read_MB_by_size':>17}" +
+           "".join(f"{n:>22}" for n in names)]
     for label, sub, grid in rows:
         vals = {}
         for n in names:
@@ -141,7 +145,12 @@ def counters_table(pmc_dirs, rows, command, cfetch_dir, cwrite_dir, copy_bytes):
                     continue
         rd = f"{vals['FETCH_SIZE'] * 1024.0 * fs / 1e6:14.1f}" if "FETCH_SIZE" in vals else f"{'-':>14}"
         wr = f"{vals['WRITE_SIZE'] * 1024.0 * ws / 1e6:14.1f}" if "WRITE_SIZE" in vals else f"{'-':>14}"
-        out.append(f"{label:<28}{rd}{wr}" +
+        sizes = [f"TCC_EA0_RDREQ_{b}B_sum" for b in (32, 64, 128)]
+        if all(k in vals for k in sizes):
+            by = f"{sum(b * vals[k] for b, k in zip((32, 64, 128), sizes)) / 1e6:17.1f}"
+        else:
+            by = f"{'-':>17}"
+        out.append(f"{label:<28}{rd}{wr}{by}" +
                    "".join(f"{vals[n]:22.1f}" if n in vals else f"{'-':>22}" for n in names))
     return "\n".join(out) + "\n"
 

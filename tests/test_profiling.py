@@ -81,6 +81,23 @@ def test_counters_table_rows_and_calibrated_bytes(tmp_path):
     assert lines[0].endswith("cmd")
     xyz = [ln for ln in lines if ln.startswith("xyz")][0].split()
     zig = [ln for ln in lines if ln.startswith("zig")][0].split()
-    # HBM read MB = 1000 KiB x 1024 x 2 (fetch scale) / 1e6; no WRITE_SIZE run: "-"
-    assert xyz[1:] == ["2.0", "-", "1000.0", "7.0"]
-    assert zig[1:] == ["6.1", "-", "3000.0", "-"]
+    # HBM read MB = 1000 KiB x 1024 x 2 (fetch scale) / 1e6; no WRITE_SIZE run
+    # and no request-size counters: "-"
+    assert xyz[1:] == ["2.0", "-", "-", "1000.0", "7.0"]
+    assert zig[1:] == ["6.1", "-", "-", "3000.0", "-"]
+
+
+def test_counters_table_bytes_by_request_size(tmp_path):
+    f = ["Counter_Name", "Kernel_Name", "Grid_Size", "Counter_Value"]
+    rows = [dict(Counter_Name=f"TCC_EA0_RDREQ_{b}B_sum", Kernel_Name="k", Grid_Size=1, Counter_Value=v)
+            for b, v in ((32, 1000.0), (64, 2000.0), (128, 3000.0))]
+    _write_csv(str(tmp_path / "r" / "x_counter_collection.csv"), rows, f)
+    _write_csv(str(tmp_path / "cf" / "x_counter_collection.csv"),
+               [dict(Counter_Name="FETCH_SIZE", Kernel_Name="copyBuffer", Grid_Size=1, Counter_Value=512.0)], f)
+    _write_csv(str(tmp_path / "cw" / "x_counter_collection.csv"),
+               [dict(Counter_Name="WRITE_SIZE", Kernel_Name="copyBuffer", Grid_Size=1, Counter_Value=1024.0)], f)
+    txt = P.counters_table([str(tmp_path / "r")], [("k", "k", None)], "cmd", str(tmp_path / "cf"),
+                           str(tmp_path / "cw"), 1024.0 * 1024)
+    line = [ln for ln in txt.splitlines() if ln.startswith("k ")][0].split()
+    # (32 * 1000 + 64 * 2000 + 128 * 3000) / 1e6 = 0.544 MB
+    assert line[3] == "0.5"
