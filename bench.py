@@ -304,6 +304,52 @@ def sweep_layouts(args, torch):
     return rows
 
 
+def sweep_cavity(args, torch):
+    """The paper's dense-geometry study (Section 4.2, Table 3 and the cavity3D
+    figures): fully fluid b^3 boxes with bounce-back walls, every kernel (the
+    read/write-only and propagation-only kernels, LBGK and LBMRT in both
+    equilibria) in FP64 and FP32, from b = 20 up; per kernel the best MFLUPS,
+    the b it was reached at, and the largest case."""
+    from paper_1611_02445_amd.lattice import Lattice, Tiling
+    sizes = (20, 32, 48, 64, 80, 100, 101, 102, 103, 128, 160, 192, 224, 252, 320, 384)
+    kernels = ("rw", "prop", "inc", "qc", "mrt-inc", "mrt-qc")
+    rows = []
+    for b in sizes:
+        tiling = Tiling(np.zeros((b, b, b), np.uint8), 0)
+        steps = int(min(2000, max(50, 4e8 / b ** 3)))
+        row = {"b": b, "nodes": b ** 3, "eta_t": round(tiling.eta_t, 4), "steps": steps}
+        for st in ("f64", "f32"):
+            for k in kernels:
+                lat = Lattice(None, 0.7, periodic=0, storage=st, model=k if k not in ("rw", "prop") else "qc",
+                              tiling=tiling)
+                lat.init()
+                if k in ("rw", "prop"):
+                    ms = _time_calib_kind(lat, 1 if k == "rw" else 2, torch, launches=steps, warmup=10)
+                else:
+                    lat.step(10)
+                    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    ev0.record(lat.stream)
+                    lat.step(steps)
+                    ev1.record(lat.stream)
+                    torch.cuda.synchronize()
+                    ms = ev0.elapsed_time(ev1) / steps
+                row[f"MFLUPS_{st}_{k}"] = round(lat.n_fluid / (ms / 1e3) / 1e6, 1)
+                del lat
+        torch.cuda.empty_cache()
+        log(f"[bench] cavity {b}^3: f64 rw {row['MFLUPS_f64_rw']} prop {row['MFLUPS_f64_prop']} "
+            f"qc {row['MFLUPS_f64_qc']} mrt-qc {row['MFLUPS_f64_mrt-qc']} | f32 qc {row['MFLUPS_f32_qc']} MFLUPS")
+        rows.append(row)
+    summary = {}
+    for key in rows[0]:
+        if not key.startswith("MFLUPS_"):
+            continue
+        best = max(rows, key=lambda r: r[key])
+        bpn = BYTES_PER_UPDATE[key.split("_")[1]]
+        summary[key[7:]] = {"max_MFLUPS": best[key], "b_at_max": best["b"], "largest_case": rows[-1][key],
+                            "bw_util_at_max": round(best[key] * 1e6 * bpn / (HBM_PEAK_GBS * 1e9), 4)}
+    return {"rows": rows, "summary": summary}
+
+
 def sweep_sphere_arrays(args, torch):
     """Random sphere arrays of diameter 40 in a 192^3 periodic box at the nine
     porosities of the paper's sparse-geometry table (Section 4.6, Table 6):
@@ -453,6 +499,8 @@ def main():
                     help="also run the 1024x512x512 FP32 forward + adjoint workload (about 2 minutes)")
     ap.add_argument("--sweep192", action="store_true",
                     help="also time the step on 192^3 random sphere arrays at porosities 0.9..0.1")
+    ap.add_argument("--sweep-cavity", action="store_true",
+                    help="also time every kernel on dense b^3 boxes (the paper's cavity3D study, Table 3)")
     ap.add_argument("--layouts", action="store_true",
                     help="also time the paper's intra-tile layout study (propagation-only kernel, Table 5)")
     ap.add_argument("--sweep-channels", action="store_true",
@@ -620,6 +668,9 @@ def main():
         torch.cuda.empty_cache()
     if args.sweep192:
         result["sphere_arrays_192"] = sweep_sphere_arrays(args, torch)
+        torch.cuda.empty_cache()
+    if args.sweep_cavity:
+        result["cavity"] = sweep_cavity(args, torch)
         torch.cuda.empty_cache()
     if args.layouts:
         result["layouts"] = sweep_layouts(args, torch)
