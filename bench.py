@@ -304,6 +304,37 @@ def sweep_layouts(args, torch):
     return rows
 
 
+def time_small_grid(args, torch):
+    """The 32^3 square duct (walls on the y and z faces, periodic in x; tau
+    0.8, g_x 1e-6), FP64, 2000 steps: plain launches against replays of the
+    32-step HIP graph (lbm_step_graphed).  A step of this grid takes about as
+    long as launching it."""
+    from paper_1611_02445_amd import inputs
+    from paper_1611_02445_amd.lattice import Lattice
+    solid = inputs.square_channel(32)
+    out = {"workload": "square duct 32^3, FP64, 2000 steps"}
+    for graphed in (False, True):
+        lat = Lattice(solid, 0.8, periodic=1)
+        lat.init()
+        lat.set_force((1e-6, 0.0, 0.0))
+        lat.step(64, graphed=graphed)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(lat.stream)
+        lat.step(2000, graphed=graphed)
+        ev1.record(lat.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = ev0.elapsed_time(ev1)
+        key = "graphed" if graphed else "plain"
+        out[key] = {"MFLUPS": round(lat.n_fluid * 2000 / (ms / 1e3) / 1e6, 1), "us_per_step": round(ms / 2, 3),
+                    "wall_us_per_step": round(wall * 1e6 / 2000, 2)}
+        del lat
+    log(f"[bench] duct 32^3: plain {out['plain']['MFLUPS']} MFLUPS, graphed {out['graphed']['MFLUPS']} MFLUPS")
+    return out
+
+
 def sweep_cavity(args, torch):
     """The paper's dense-geometry study (Section 4.2, Table 3 and the cavity3D
     figures): fully fluid b^3 boxes with bounce-back walls, every kernel (the
@@ -660,6 +691,7 @@ def main():
     result["mrt_quasi_compressible"] = mrt
     del r, lat
     torch.cuda.empty_cache()
+    result["small_grid"] = time_small_grid(args, torch)
     if args.adj_steps > 0:
         result["adjoint"] = time_adjoint(args, torch)
         torch.cuda.empty_cache()

@@ -196,6 +196,16 @@ int lbm_set_boundaries(lbm_ctx *ctx, const uint8_t *type_host, double ux, double
  * two lattices (Alg. 2).  Asynchronous. */
 int lbm_step(lbm_ctx *ctx, int32_t n);
 
+/* The same n steps as lbm_step, bitwise, launched as replays of a HIP graph
+ * of 32 steps (the remainder n mod 32 as plain launches): for small grids,
+ * where launching a kernel costs as much as running it.  The graph is
+ * captured on first use from either lattice parity (on a private stream of
+ * the context) and captured again whenever a kernel argument has changed
+ * since (force, boundaries, parameters).  Asynchronous on the context's
+ * stream.  LBM_E_UNSUPPORTED for FP16 storage with stochastic rounding,
+ * whose random bits change with every launch. */
+int lbm_step_graphed(lbm_ctx *ctx, int32_t n);
+
 /* One step from lattice `src` to lattice `dst` (any caller buffers of
  * state_bytes, e.g. checkpoint slots; src != dst).  Does not change which
  * lattice is current. */

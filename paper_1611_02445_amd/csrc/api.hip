@@ -15,6 +15,21 @@
 
 using namespace tlbm;
 
+// A replayable chunk of steps: GRAPH_STEPS launches captured once from one
+// lattice parity with the kernel arguments in P.
+constexpr int32_t GRAPH_STEPS = 32;
+struct StepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Phys P{};
+    void release() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+};
+
 struct lbm_ctx {
     lbm_params params;
     int32_t nx, ny, nz, periodic;
@@ -30,6 +45,13 @@ struct lbm_ctx {
     size_t state_bytes;
     int device;
     std::vector<int32_t> corner;  // [n_tiles][3] tile corners in device order (host copy)
+    StepGraph graphs[2];          // lbm_step_graphed, by starting parity
+    hipStream_t capture = nullptr;  // private stream the graphs are captured on
+    ~lbm_ctx() {
+        graphs[0].release();
+        graphs[1].release();
+        if (capture) (void)hipStreamDestroy(capture);
+    }
 };
 
 namespace {
@@ -385,6 +407,64 @@ extern "C" int lbm_step(lbm_ctx *c, int32_t n) {
         c->cur ^= 1;
     }
     return LBM_OK;
+}
+
+// Capture GRAPH_STEPS steps from the current lattice with the kernel
+// arguments P, on the context's private stream (the caller's stream is not
+// put into capture mode).
+static int capture_steps(lbm_ctx *c, StepGraph &g, const Phys &P) {
+    g.release();
+    hipError_t e = hipSuccess;
+    if (!c->capture) e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "lbm_step_graphed: capture stream");
+    Launch L = c->L;
+    L.stream = c->capture;
+    e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "lbm_step_graphed: begin capture");
+    void *x = cur_state(c), *y = c->cur ? c->a : c->b;
+    for (int32_t s = 0; s < GRAPH_STEPS && e == hipSuccess; ++s) {
+        e = launch_step(L, P, x, y);
+        std::swap(x, y);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e_end = hipStreamEndCapture(c->capture, &graph);  // always leave capture mode
+    if (e == hipSuccess) e = e_end;
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        g.exec = nullptr;
+        return hip_fail(e, "lbm_step_graphed: capture");
+    }
+    g.graph = graph;
+    g.P = P;
+    return LBM_OK;
+}
+
+extern "C" int lbm_step_graphed(lbm_ctx *c, int32_t n) {
+    CHECK_CTX(c);
+    if (n < 0) return fail(LBM_E_INVAL, "lbm_step_graphed: negative step count");
+    if (c->P.storage == LBM_F16S && c->P.f16_stochastic)
+        return fail(LBM_E_UNSUPPORTED, "lbm_step_graphed: stochastic FP16 rounding draws new bits every launch, "
+                                       "which a replayed graph would repeat");
+    const int32_t chunks = c->n_tiles > 0 ? n / GRAPH_STEPS : 0;
+    if (chunks > 0) {
+        // the captured arguments: everything but the launch counter, which
+        // only stochastic rounding reads
+        Phys key = c->P;
+        key.launch_counter = 0;
+        StepGraph &g = c->graphs[c->cur];
+        if (!g.exec || std::memcmp(&g.P, &key, sizeof(Phys)) != 0) {
+            const int rc = capture_steps(c, g, key);
+            if (rc) return rc;
+        }
+        for (int32_t k = 0; k < chunks; ++k) {
+            const hipError_t e = hipGraphLaunch(g.exec, c->stream);
+            if (e != hipSuccess) return hip_fail(e, "lbm_step_graphed: launch");
+        }
+        // an even number of steps: the same lattice is current again
+        c->P.launch_counter += (uint32_t)(chunks * GRAPH_STEPS);
+    }
+    return lbm_step(c, n - chunks * GRAPH_STEPS);
 }
 
 extern "C" int lbm_step_buf(lbm_ctx *c, const void *src, void *dst) {

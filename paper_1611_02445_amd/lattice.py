@@ -175,8 +175,10 @@ class Lattice:
         call("lbm_set_boundaries", self.ctx, t.ctypes.data_as(ctypes.c_void_p), *map(float, u_in), float(rho_out),
              _vp(self.bc_buf))
 
-    def step(self, n=1):
-        call("lbm_step", self.ctx, int(n))
+    def step(self, n=1, graphed=False):
+        """n steps; graphed=True replays a captured HIP graph of 32 steps
+        (same results, less launch overhead on small grids)."""
+        call("lbm_step_graphed" if graphed else "lbm_step", self.ctx, int(n))
 
     def step_buf(self, src, dst):
         call("lbm_step_buf", self.ctx, _vp(src), _vp(dst))
