@@ -57,10 +57,10 @@ def lib():
         L.oracle_macroscopic.argtypes = [P, P, i32, i32, i32, i32, P, f64, f64, f64, P, P]
         L.oracle_pull.argtypes = [P, P, P, i32, i32, i32, i32]
         L.oracle_pull_transpose.argtypes = [P, P, P, i32, i32, i32, i32]
-        L.oracle_collide_jt_node.argtypes = [P, P, f64, P, P, P]
-        L.oracle_loss_ux.argtypes = [P, P, i32, i32, i32, P, P, P]
+        L.oracle_collide_jt_node.argtypes = [i32, P, P, f64, P, P, P]
+        L.oracle_loss_ux.argtypes = [i32, P, P, i32, i32, i32, P, P, P]
         L.oracle_loss_ux.restype = f64
-        L.oracle_adjoint.argtypes = [P, P, i32, i32, i32, i32, f64, P, i32, P, P]
+        L.oracle_adjoint.argtypes = [i32, P, P, i32, i32, i32, i32, f64, P, i32, P, P]
         L.oracle_adjoint.restype = f64
         L.oracle_mrt_matrix.argtypes = [P, P]
         L.oracle_mrt_rates.argtypes = [f64, P]
@@ -159,10 +159,11 @@ def collide_node(fin, F, tau, model=0):
     return out
 
 
-def collide_jt_node(fin, F, tau, lam):
+def collide_jt_node(fin, F, tau, lam, model=0):
     eta = np.zeros(Q)
     gF = np.zeros(3)
-    lib().oracle_collide_jt_node(_p(_f64(fin)), _p(_f64(F)), float(tau), _p(_f64(lam)), _p(eta), _p(gF))
+    lib().oracle_collide_jt_node(int(model), _p(_f64(fin)), _p(_f64(F)), float(tau), _p(_f64(lam)), _p(eta),
+                                 _p(gF))
     return eta, gF
 
 
@@ -269,15 +270,15 @@ def pull_transpose(mu, solid, periodic=0):
     return out
 
 
-def loss_ux(s, solid, force_field=None):
+def loss_ux(s, solid, force_field=None, model=0):
     solid = _u8(solid)
     nz, ny, nx = solid.shape
     s = _f64(s)
     ff = None if force_field is None else _f64(force_field)
-    return lib().oracle_loss_ux(_p(s), _p(solid), nx, ny, nz, _p(ff), None, None)
+    return lib().oracle_loss_ux(int(model), _p(s), _p(solid), nx, ny, nz, _p(ff), None, None)
 
 
-def adjoint(s0, solid, tau, force_field, T, periodic=0):
+def adjoint(s0, solid, tau, force_field, T, periodic=0, model=0):
     """Returns (L, dL/ds0 [19,...], dL/dF [3,...]) for L = mean u_x at step T."""
     solid = _u8(solid)
     nz, ny, nx = solid.shape
@@ -285,7 +286,8 @@ def adjoint(s0, solid, tau, force_field, T, periodic=0):
     ff = _f64(force_field)
     gs = np.zeros_like(s0)
     gF = np.zeros_like(ff)
-    L = lib().oracle_adjoint(_p(s0), _p(solid), nx, ny, nz, periodic, tau, _p(ff), int(T), _p(gs), _p(gF))
+    L = lib().oracle_adjoint(int(model), _p(s0), _p(solid), nx, ny, nz, periodic, tau, _p(ff), int(T), _p(gs),
+                             _p(gF))
     if not np.isfinite(L):
         raise MemoryError("oracle_adjoint: allocation failed")
     return L, gs, gF

@@ -526,7 +526,8 @@ void oracle_macroscopic(const double *f, const uint8_t *solid, int32_t nx, int32
  *     eta_t         = J_t^T lambda_t,   J_t = dC/dg at g_t = S s_{t-1}
  *     dL/dF        += (dC/dF)^T lambda_t
  *     lambda_{t-1}  = S^T eta_t
- * and dL/ds_0 = lambda_0.  Only the quasi-compressible model is provided. */
+ * and dL/ds_0 = lambda_0.  Provided for the two single-relaxation-time
+ * models (quasi-compressible, Eq. 3 and 5; incompressible, Eq. 4 and 6). */
 
 /* S as an operator on a whole field: g = S s (solid nodes of g set to 0) */
 void oracle_pull(const double *s, double *g, const uint8_t *solid, int32_t nx, int32_t ny, int32_t nz,
@@ -571,18 +572,27 @@ void oracle_pull_transpose(const double *mu, double *out, const uint8_t *solid, 
             }
 }
 
-/* derivatives of the quasi-compressible collision at one node.
+/* derivatives of the single-relaxation-time collision at one node (model 0
+ * quasi-compressible, 1 incompressible).
  * Returns (J^T lam)_j in eta[19] and (dC/dF)^T lam in gF[3].
  *   dC_i/dg_j = (1 - 1/tau) delta_ij + (1/tau) dfeq_i/dg_j + dS_i/dg_j
- *   dfeq_i/dg_j = dfeq_i/drho + dfeq_i/du . du/dg_j,   du/dg_j = (c_j - u)/rho
+ *   dfeq_i/dg_j = dfeq_i/drho + dfeq_i/du . du/dg_j
+ * quasi-compressible (Eq. 3, u = (j + F/2)/rho, Eq. 5):
+ *   du/dg_j = (c_j - u)/rho,  du/dF = I/(2 rho)
  *   dfeq_i/drho = w_i (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
  *   dfeq_i/du   = w_i rho (3 c_i + 9 (c_i.u) c_i - 3 u)
+ * incompressible (Eq. 4, u = j + F/2, Eq. 6):
+ *   du/dg_j = c_j,  du/dF = I/2
+ *   dfeq_i/drho = w_i
+ *   dfeq_i/du   = w_i (3 c_i + 9 (c_i.u) c_i - 3 u)
+ * both:
  *   dS_i/du     = (1 - 1/(2tau)) w_i (9 (c_i.F) c_i - 3 F)
- *   dS_i/dF|_u  = (1 - 1/(2tau)) w_i (3 (c_i - u) + 9 (c_i.u) c_i),  du/dF = I/(2 rho) */
-void oracle_collide_jt_node(const double *fin, const double *F, double tau, const double *lam, double *eta,
-                            double *gF) {
+ *   dS_i/dF|_u  = (1 - 1/(2tau)) w_i (3 (c_i - u) + 9 (c_i.u) c_i) */
+void oracle_collide_jt_node(int32_t model, const double *fin, const double *F, double tau, const double *lam,
+                            double *eta, double *gF) {
+    const int inc = model == 1;
     double rho, u[3];
-    moments(0, fin, F, &rho, u);
+    moments(model, fin, F, &rho, u);
     double k = 1.0 - 1.0 / (2.0 * tau);
     double A = 0.0, V[3] = {0.0, 0.0, 0.0}, D[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < Q; ++i) {
@@ -590,10 +600,10 @@ void oracle_collide_jt_node(const double *fin, const double *F, double tau, cons
         double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
         double cF = c[0] * F[0] + c[1] * F[1] + c[2] * F[2];
         double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-        double dfeq_drho = WT(i) * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        double dfeq_drho = inc ? WT(i) : WT(i) * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
         A += lam[i] * dfeq_drho / tau;
         for (int a = 0; a < 3; ++a) {
-            double dfeq_du = WT(i) * rho * (3.0 * c[a] + 9.0 * cu * c[a] - 3.0 * u[a]);
+            double dfeq_du = WT(i) * (inc ? 1.0 : rho) * (3.0 * c[a] + 9.0 * cu * c[a] - 3.0 * u[a]);
             double dS_du = k * WT(i) * (9.0 * cF * c[a] - 3.0 * F[a]);
             V[a] += lam[i] * (dfeq_du / tau + dS_du);
             D[a] += lam[i] * k * WT(i) * (3.0 * (c[a] - u[a]) + 9.0 * cu * c[a]);
@@ -601,16 +611,18 @@ void oracle_collide_jt_node(const double *fin, const double *F, double tau, cons
     }
     for (int j = 0; j < Q; ++j) {
         double cj_u = 0.0;
-        for (int a = 0; a < 3; ++a) cj_u += V[a] * (CV[j][a] - u[a]);
-        eta[j] = (1.0 - 1.0 / tau) * lam[j] + A + cj_u / rho;
+        for (int a = 0; a < 3; ++a) cj_u += V[a] * (inc ? CV[j][a] : (CV[j][a] - u[a]) / rho);
+        eta[j] = (1.0 - 1.0 / tau) * lam[j] + A + cj_u;
     }
-    for (int a = 0; a < 3; ++a) gF[a] = V[a] / (2.0 * rho) + D[a];
+    for (int a = 0; a < 3; ++a) gF[a] = V[a] / (inc ? 2.0 : 2.0 * rho) + D[a];
 }
 
-/* loss L = (1/N_f) sum_fluid u_x(s) with u_x = (sum c_x s - F_x/2)/rho.  When
- * lam != NULL also returns dL/ds in lam[19][N] and adds dL/dF_x to gF. */
-double oracle_loss_ux(const double *s, const uint8_t *solid, int32_t nx, int32_t ny, int32_t nz,
+/* loss L = (1/N_f) sum_fluid u_x(s) with u_x = (sum c_x s - F_x/2)/rho
+ * (model 0) or sum c_x s - F_x/2 (model 1).  When lam != NULL also returns
+ * dL/ds in lam[19][N] and adds dL/dF_x to gF. */
+double oracle_loss_ux(int32_t model, const double *s, const uint8_t *solid, int32_t nx, int32_t ny, int32_t nz,
                       const double *force, double *lam, double *gF) {
+    const int inc = model == 1;
     long N = (long)nx * ny * nz, nf = 0;
     for (long n = 0; n < N; ++n) nf += !solid[n];
     double L = 0.0;
@@ -626,11 +638,12 @@ double oracle_loss_ux(const double *s, const uint8_t *solid, int32_t nx, int32_t
             jx += CV[i][0] * s[(long)i * N + n];
         }
         double Fx = force ? force[n] : 0.0;
-        double ux = (jx - 0.5 * Fx) / r;
+        double ux = inc ? jx - 0.5 * Fx : (jx - 0.5 * Fx) / r;
         L += ux;
         if (lam) {
-            for (int i = 0; i < Q; ++i) lam[(long)i * N + n] = (CV[i][0] - ux) / r / (double)nf;
-            if (gF) gF[n] += -0.5 / r / (double)nf;
+            for (int i = 0; i < Q; ++i)
+                lam[(long)i * N + n] = (inc ? CV[i][0] : (CV[i][0] - ux) / r) / (double)nf;
+            if (gF) gF[n] += -0.5 / (inc ? 1.0 : r) / (double)nf;
         }
     }
     return L / (double)nf;
@@ -640,7 +653,7 @@ double oracle_loss_ux(const double *s, const uint8_t *solid, int32_t nx, int32_t
  * F[3][N], loss = mean u_x at step T.  Writes dL/ds0 [19][N] and dL/dF [3][N];
  * returns L.  Keeps all T+1 states (small boxes only).  Returns NaN on
  * allocation failure. */
-double oracle_adjoint(const double *s0, const uint8_t *solid, int32_t nx, int32_t ny, int32_t nz,
+double oracle_adjoint(int32_t model, const double *s0, const uint8_t *solid, int32_t nx, int32_t ny, int32_t nz,
                       int32_t periodic, double tau, const double *force, int32_t T, double *grad_s0,
                       double *grad_F) {
     long N = (long)nx * ny * nz;
@@ -655,11 +668,11 @@ double oracle_adjoint(const double *s0, const uint8_t *solid, int32_t nx, int32_
     }
     memcpy(states, s0, sizeof(double) * SZ);
     for (int t = 1; t <= T; ++t)
-        oracle_step(states + (size_t)(t - 1) * SZ, states + (size_t)t * SZ, solid, nx, ny, nz, periodic, 0, tau,
+        oracle_step(states + (size_t)(t - 1) * SZ, states + (size_t)t * SZ, solid, nx, ny, nz, periodic, model, tau,
                     force, 0.0, 0.0, 0.0);
     for (int a = 0; a < 3; ++a)
         for (long n = 0; n < N; ++n) grad_F[(long)a * N + n] = 0.0;
-    double L = oracle_loss_ux(states + (size_t)T * SZ, solid, nx, ny, nz, force, lam, grad_F);
+    double L = oracle_loss_ux(model, states + (size_t)T * SZ, solid, nx, ny, nz, force, lam, grad_F);
     for (int t = T; t >= 1; --t) {
         oracle_pull(states + (size_t)(t - 1) * SZ, g, solid, nx, ny, nz, periodic);
         memset(eta, 0, sizeof(double) * SZ);
@@ -671,7 +684,7 @@ double oracle_adjoint(const double *s0, const uint8_t *solid, int32_t nx, int32_
                 l[i] = lam[(long)i * N + n];
             }
             force_at(force, N, n, 0.0, 0.0, 0.0, F);
-            oracle_collide_jt_node(fin, F, tau, l, e, dF);
+            oracle_collide_jt_node(model, fin, F, tau, l, e, dF);
             for (int i = 0; i < Q; ++i) eta[(long)i * N + n] = e[i];
             for (int a = 0; a < 3; ++a) grad_F[(long)a * N + n] += dF[a];
         }

@@ -25,40 +25,54 @@ def test_pull_transpose_dot_product():
         assert abs(lhs - rhs) <= 1e-14 * np.sum(np.abs(O.pull(v, solid, periodic) * w))
 
 
-def test_collision_jt_against_central_differences():
+@pytest.mark.parametrize("model", [0, 1])
+def test_collision_jt_against_central_differences(model):
     c, w, _ = O.lattice()
     rng = np.random.default_rng(2)
     for tau in (0.6, 0.8, 1.4):
         fin = w * (1 + 0.05 * rng.uniform(-1, 1, 19))
         F = 1e-4 * rng.uniform(-1, 1, 3)
         lam = rng.normal(size=19)
-        eta, gF = O.collide_jt_node(fin, F, tau, lam)
+        eta, gF = O.collide_jt_node(fin, F, tau, lam, model=model)
         h = 1e-6
         for j in range(19):
             e = np.zeros(19)
             e[j] = h
-            d = (O.collide_node(fin + e, F, tau) - O.collide_node(fin - e, F, tau)) / (2 * h)
+            d = (O.collide_node(fin + e, F, tau, model=model) - O.collide_node(fin - e, F, tau, model=model)) / (2 * h)
             assert abs(d @ lam - eta[j]) <= 1e-8 * (1 + abs(eta[j]))
         for a in range(3):
             e = np.zeros(3)
             e[a] = h
-            d = (O.collide_node(fin, F + e, tau) - O.collide_node(fin, F - e, tau)) / (2 * h)
+            d = (O.collide_node(fin, F + e, tau, model=model) - O.collide_node(fin, F - e, tau, model=model)) / (2 * h)
             assert abs(d @ lam - gF[a]) <= 1e-8 * (1 + abs(gF[a]))
 
 
-def test_adjoint_against_finite_differences():
+def test_incompressible_jt_differs_from_quasi_compressible():
+    """The two models' Jacobians are not the same map (a test that passed
+    for both with one formula would not pin the second)."""
+    c, w, _ = O.lattice()
+    rng = np.random.default_rng(4)
+    fin = w * (1 + 0.05 * rng.uniform(-1, 1, 19))
+    lam = rng.normal(size=19)
+    e0, _ = O.collide_jt_node(fin, np.zeros(3), 0.8, lam, model=0)
+    e1, _ = O.collide_jt_node(fin, np.zeros(3), 0.8, lam, model=1)
+    assert np.abs(e0 - e1).max() > 1e-4 * np.abs(e0).max()
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_adjoint_against_finite_differences(model):
     solid = _geom()
     tau, T = 0.8, 12
     rng = np.random.default_rng(3)
     shape = solid.shape
     fl = solid == 0
-    s0 = O.init(solid) * (1 + 0.01 * rng.uniform(-1, 1, (19,) + shape))
+    s0 = O.init(solid, model=model) * (1 + 0.01 * rng.uniform(-1, 1, (19,) + shape))
     force = np.zeros((3,) + shape)
     force[0] = rng.normal(1e-5, 1e-6, shape) * fl
-    L, gs, gF = O.adjoint(s0, solid, tau, force, T, periodic=7)
+    L, gs, gF = O.adjoint(s0, solid, tau, force, T, periodic=7, model=model)
 
     def loss(s, ff):
-        return O.loss_ux(O.run(s, solid, tau, T, force=ff, periodic=7), solid, ff)
+        return O.loss_ux(O.run(s, solid, tau, T, force=ff, periodic=7, model=model), solid, ff, model=model)
 
     assert abs(loss(s0, force) - L) <= 1e-15 * abs(L) + 1e-20
     nodes = np.flatnonzero(fl.ravel())
