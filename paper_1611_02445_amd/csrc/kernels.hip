@@ -975,10 +975,12 @@ __global__ __launch_bounds__(512) void k_tiles_to_dense(KArgs a, const T *in, in
 }
 
 // ---------------------------------------------------------------------------
-// discrete adjoint (quasi-compressible, runs layout; FP64 storage with FP64
-// arithmetic or FP32 storage with FP32 arithmetic, gradient sums in FP64)
+// discrete adjoint (single-relaxation-time models, runs layout; FP64 storage
+// with FP64 arithmetic or FP32 storage with FP32 arithmetic, gradient sums in
+// FP64)
 //
-// For the local collision C(g, F) with rho = sum g, u = (sum c g + F/2)/rho:
+// For the quasi-compressible collision C(g, F) with rho = sum g,
+// u = (sum c g + F/2)/rho (Eq. 3, 5):
 //   (J^T lam)_j = (1 - 1/tau) lam_j + A + V.(c_j - u)/rho
 //   A   = (1/tau) sum_i lam_i w_i (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
 //   V   = sum_i lam_i [ (rho/tau) w_i (3 c_i + 9 (c_i.u) c_i - 3 u)
@@ -989,8 +991,13 @@ __global__ __launch_bounds__(512) void k_tiles_to_dense(KArgs a, const T *in, in
 // rho and j = sum c g, so the forward values may be the shifted ones
 // d = g - w rho_base (rho = rho_base + sum d, j = sum c d).  The adjoint
 // values themselves are never shifted.
+// For the incompressible collision (Eq. 4, 6: feq linear in rho with the
+// velocity terms not scaled by it, u = sum c g + F/2), du/dg_j = c_j and
+// dfeq_i/drho = w_i, so
+//   (J^T lam)_j = (1 - 1/tau) lam_j + q/tau + V.c_j,   (dC/dF)^T lam = V/2 + ...
+// with V as above but 1/tau in place of rho/tau.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int INC = 0>
 __device__ __forceinline__ void collide_jt(const T (&d)[Q], T rho_base, const T (&lam)[Q], T omega, T kg, T Fx, T Fy,
                                            T Fz, T (&eta)[Q], T &gx, T &gy, T &gz) {
     T drho = 0, jx = 0, jy = 0, jz = 0;
@@ -1002,10 +1009,13 @@ __device__ __forceinline__ void collide_jt(const T (&d)[Q], T rho_base, const T 
         jz += T(CZ[i]) * d[i];
     }
     const T rho = rho_base + drho;
-    const T ir = T(1) / rho;
+    T ir = T(1), ro = omega;
+    if constexpr (!INC) {
+        ir = T(1) / rho;
+        ro = rho * omega;
+    }
     const T ux = (jx + T(0.5) * Fx) * ir, uy = (jy + T(0.5) * Fy) * ir, uz = (jz + T(0.5) * Fz) * ir;
     const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
-    const T ro = rho * omega;
     // rest direction
     T q = lam[0] * T(weight(0));
     T A = q * (T(1) - usq);
@@ -1032,7 +1042,7 @@ __device__ __forceinline__ void collide_jt(const T (&d)[Q], T rho_base, const T 
         if (CY[i]) { py += T(CY[i]) * pi; ry += T(CY[i]) * ri; }
         if (CZ[i]) { pz += T(CZ[i]) * pi; rz += T(CZ[i]) * ri; }
     }
-    A *= omega;
+    A = INC ? q * omega : A * omega;
     const T Vx = px - q * (T(3) * ro * ux + T(3) * kg * Fx);
     const T Vy = py - q * (T(3) * ro * uy + T(3) * kg * Fy);
     const T Vz = pz - q * (T(3) * ro * uz + T(3) * kg * Fz);
@@ -1040,7 +1050,8 @@ __device__ __forceinline__ void collide_jt(const T (&d)[Q], T rho_base, const T 
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
         const T Vc = T(CX[j]) * Vx + T(CY[j]) * Vy + T(CZ[j]) * Vz;
-        eta[j] = (T(1) - omega) * lam[j] + A + (Vc - Vu) * ir;
+        if constexpr (INC) eta[j] = (T(1) - omega) * lam[j] + A + Vc;
+        else eta[j] = (T(1) - omega) * lam[j] + A + (Vc - Vu) * ir;
     }
     gx = T(0.5) * Vx * ir + kg * (rx - T(3) * q * ux);
     gy = T(0.5) * Vy * ir + kg * (ry - T(3) * q * uy);
@@ -1060,9 +1071,12 @@ struct AdjArgs {
 };
 
 // seed: from s_{T-1}: g_T = S s_{T-1}, s_T = C(g_T), lam_T = dL/ds_T,
-// eta_T = J_T^T lam_T, grad = rho0 [(dC/dF)^T lam_T + dL/dF]
-template <int ST, typename OffT>
+// eta_T = J_T^T lam_T, grad = rho0 [(dC/dF)^T lam_T + dL/dF].  With
+// u_x = (sum c_x s - F_x/2)/rho (quasi-compressible) lam_T depends on s_T; with
+// u_x = sum c_x s - F_x/2 (incompressible) it is c_x / N_fluid.
+template <int ST, int MODEL, typename OffT>
 __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
+    constexpr int INC = MODEL == LBM_INCOMPRESSIBLE;
     using T = typename Codec<ST>::S;
     const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
@@ -1080,22 +1094,28 @@ __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
         gather_all<false, true, T, OffT>(g, h, a.s, me, lane);
         T Fx, Fy, Fz;
         load_force<T>(a.P, t, lane, Fx, Fy, Fz);
-        T s[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) s[i] = g[i];
-        collide<T, LBM_QUASI_COMPRESSIBLE>(s, rb, om, kg, Fx, Fy, Fz);
-        T drT = 0, jx = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            drT += s[i];
-            jx += T(CX[i]) * s[i];
-        }
-        const T irT = T(1) / (rb + drT);
-        const T uxT = (jx - T(0.5) * Fx) * irT;
         T lam[Q];
+        T irT = T(1);
+        if constexpr (INC) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) lam[i] = (T(CX[i]) - uxT) * irT * inv_n;
-        collide_jt<T>(g, rb, lam, om, kg, Fx, Fy, Fz, eta, gx, gy, gz);
+            for (int i = 0; i < Q; ++i) lam[i] = T(CX[i]) * inv_n;
+        } else {
+            T s[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) s[i] = g[i];
+            collide<T, LBM_QUASI_COMPRESSIBLE>(s, rb, om, kg, Fx, Fy, Fz);
+            T drT = 0, jx = 0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                drT += s[i];
+                jx += T(CX[i]) * s[i];
+            }
+            irT = T(1) / (rb + drT);
+            const T uxT = (jx - T(0.5) * Fx) * irT;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) lam[i] = (T(CX[i]) - uxT) * irT * inv_n;
+        }
+        collide_jt<T, INC>(g, rb, lam, om, kg, Fx, Fy, Fz, eta, gx, gy, gz);
         gx += T(-0.5) * irT * inv_n;
     }
     store_tile<T, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
@@ -1107,7 +1127,7 @@ __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
 
 // step: lam_{t-1} = S^T eta_t (reverse gather), g_{t-1} = S s_{t-2},
 // eta_{t-1} = J^T lam_{t-1}, grad += rho0 (dC/dF)^T lam_{t-1}
-template <int ST, typename OffT>
+template <int ST, int MODEL, typename OffT>
 __global__ __launch_bounds__(512) void k_adj_step(AdjArgs a) {
     using T = typename Codec<ST>::S;
     const int t = wave_tile(a.wpb, a.nblocks);
@@ -1126,7 +1146,8 @@ __global__ __launch_bounds__(512) void k_adj_step(AdjArgs a) {
         T Fx, Fy, Fz;
         load_force<T>(a.P, t, lane, Fx, Fy, Fz);
         T gx, gy, gz;
-        collide_jt<T>(g, T(a.P.rho_base), lam, T(a.P.omega), T(a.P.kg), Fx, Fy, Fz, eta, gx, gy, gz);
+        collide_jt<T, MODEL == LBM_INCOMPRESSIBLE>(g, T(a.P.rho_base), lam, T(a.P.omega), T(a.P.kg), Fx, Fy, Fz, eta,
+                                                   gx, gy, gz);
         double *go = a.grad + (size_t)t * 3 * TILE + lane;
         go[0] += a.P.rho0 * (double)gx;
         go[TILE] += a.P.rho0 * (double)gy;
@@ -1136,7 +1157,7 @@ __global__ __launch_bounds__(512) void k_adj_step(AdjArgs a) {
 }
 
 // final: lam_0 = S^T eta_1
-template <int ST, typename OffT>
+template <int ST, int MODEL, typename OffT>
 __global__ __launch_bounds__(512) void k_adj_final(AdjArgs a) {
     using T = typename Codec<ST>::S;
     const int t = wave_tile(a.wpb, a.nblocks);
@@ -1348,27 +1369,33 @@ static AdjArgs make_adj(const Launch &L, const Phys &P, const void *s, const voi
     return a;
 }
 
-// the adjoint kernels exist for FP64 and FP32 storage (runs layout)
-template <int ST, typename OffT>
+// the adjoint kernels exist for FP64 and FP32 storage (runs layout) and the
+// two single-relaxation-time models; the final reverse gather has no model
+template <int ST, int MODEL, typename OffT>
 struct SeedK {
-    static constexpr auto fn = k_adj_seed<ST, OffT>;
+    static constexpr auto fn = k_adj_seed<ST, MODEL, OffT>;
 };
-template <int ST, typename OffT>
+template <int ST, int MODEL, typename OffT>
 struct StepK {
-    static constexpr auto fn = k_adj_step<ST, OffT>;
+    static constexpr auto fn = k_adj_step<ST, MODEL, OffT>;
 };
-template <int ST, typename OffT>
+template <int ST, int MODEL, typename OffT>
 struct FinalK {
-    static constexpr auto fn = k_adj_final<ST, OffT>;
+    static constexpr auto fn = k_adj_final<ST, LBM_QUASI_COMPRESSIBLE, OffT>;
 };
 
-template <template <int, typename> class K>
+template <template <int, int, typename> class K, int MODEL>
+static void (*adj_fn(const Launch &L, bool f32))(AdjArgs) {
+    if (L.off32) return f32 ? K<LBM_F32, MODEL, uint32_t>::fn : K<LBM_F64, MODEL, uint32_t>::fn;
+    return f32 ? K<LBM_F32, MODEL, uint64_t>::fn : K<LBM_F64, MODEL, uint64_t>::fn;
+}
+
+template <template <int, int, typename> class K>
 static hipError_t launch_adj(const Launch &L, const AdjArgs &a) {
     if (L.n_tiles == 0) return hipSuccess;
     const bool f32 = a.P.storage == LBM_F32;
-    void (*fn)(AdjArgs);
-    if (L.off32) fn = f32 ? K<LBM_F32, uint32_t>::fn : K<LBM_F64, uint32_t>::fn;
-    else fn = f32 ? K<LBM_F32, uint64_t>::fn : K<LBM_F64, uint64_t>::fn;
+    void (*fn)(AdjArgs) = a.P.model == LBM_INCOMPRESSIBLE ? adj_fn<K, LBM_INCOMPRESSIBLE>(L, f32)
+                                                            : adj_fn<K, LBM_QUASI_COMPRESSIBLE>(L, f32);
     hipLaunchKernelGGL(fn, dim3(L.grid), block_of(L), 0, L.stream, a);
     return hipGetLastError();
 }

@@ -22,8 +22,9 @@ def _force_field(sp, seed, mean=1e-5, std=1e-6):
     return g
 
 
-@pytest.mark.parametrize("periodic,K", [(7, 5), (0, 3), (5, 12)])
-def test_adjoint_matches_oracle(periodic, K):
+@pytest.mark.parametrize("periodic,K,model", [(7, 5, "qc"), (0, 3, "qc"), (5, 12, "qc"), (7, 5, "inc"),
+                                               (0, 3, "inc")])
+def test_adjoint_matches_oracle(periodic, K, model):
     import torch
     from paper_1611_02445_amd.autograd import CheckpointedAdjoint
     tau, T = 0.8, 12
@@ -31,9 +32,9 @@ def test_adjoint_matches_oracle(periodic, K):
     sp = padded(s, periodic)
     f0 = perturbed_state(sp, 3)
     g = _force_field(sp, 4)
-    log(f"[case] adjoint vs oracle periodic={periodic} K={K} T={T}")
-    Lo, gs_o, gF_o = O.adjoint(f0, sp, tau, g, T, periodic=periodic)
-    lat = new_lattice(s, tau, periodic)
+    log(f"[case] adjoint vs oracle periodic={periodic} K={K} T={T} model={model}")
+    Lo, gs_o, gF_o = O.adjoint(f0, sp, tau, g, T, periodic=periodic, model=O.MODELS[model])
+    lat = new_lattice(s, tau, periodic, model=model)
     lat.set_force(torch.from_numpy(g).cuda())
     run = CheckpointedAdjoint(lat, T, K)
     L = run.forward(torch.from_numpy(f0))
@@ -176,8 +177,8 @@ def test_adjoint_full_size_finite_differences():
 F32_EPS = 2.0 ** -24
 
 
-@pytest.mark.parametrize("periodic,K,K2", [(7, 5, None), (0, 6, 2)])
-def test_adjoint_f32_matches_oracle(periodic, K, K2):
+@pytest.mark.parametrize("periodic,K,K2,model", [(7, 5, None, "qc"), (0, 6, 2, "qc"), (7, 4, None, "inc")])
+def test_adjoint_f32_matches_oracle(periodic, K, K2, model):
     import torch
     from paper_1611_02445_amd.autograd import CheckpointedAdjoint
     tau, T = 0.8, 12
@@ -185,9 +186,9 @@ def test_adjoint_f32_matches_oracle(periodic, K, K2):
     sp = padded(s, periodic)
     f0 = perturbed_state(sp, 5)
     g = _force_field(sp, 6)
-    log(f"[case] f32 adjoint vs oracle periodic={periodic} K={K} K2={K2} T={T}")
-    Lo, gs_o, gF_o = O.adjoint(f0, sp, tau, g, T, periodic=periodic)
-    lat = new_lattice(s, tau, periodic, storage="f32")
+    log(f"[case] f32 adjoint vs oracle periodic={periodic} K={K} K2={K2} T={T} model={model}")
+    Lo, gs_o, gF_o = O.adjoint(f0, sp, tau, g, T, periodic=periodic, model=O.MODELS[model])
+    lat = new_lattice(s, tau, periodic, storage="f32", model=model)
     lat.set_force(torch.from_numpy(g).cuda())
     run = CheckpointedAdjoint(lat, T, K, K2)
     L = run.forward(torch.from_numpy(f0))
@@ -199,7 +200,8 @@ def test_adjoint_f32_matches_oracle(periodic, K, K2):
     eg = np.max(np.abs(gg[:, fl] - gF_o[:, fl])) / np.abs(gF_o[:, fl]).max()
     # the loss is a mean of u_x; each u_x carries at most the same relative
     # rounding bound times max|u|
-    _, u = O.macroscopic(O.run(f0, sp, tau, T, force=g, periodic=periodic), sp, force=g)
+    mi = O.MODELS[model]
+    _, u = O.macroscopic(O.run(f0, sp, tau, T, force=g, periodic=periodic, model=mi), sp, force=g, model=mi)
     umax = np.abs(u[:, fl]).max()
     log(f"   L {L:.9e} vs {Lo:.9e} (tol {tol * umax:.2e});  dL/ds0 err {es:.2e}  dL/dg err {eg:.2e}  tol {tol:.2e}")
     assert abs(L - Lo) <= tol * umax
@@ -306,3 +308,13 @@ def test_adjoint_independent_of_launch_configuration(storage):
     for L, gs, gg in out[1:]:
         assert abs(L - out[0][0]) <= 1e-14 * abs(out[0][0])
         assert np.array_equal(gs, out[0][1]) and np.array_equal(gg, out[0][2])
+
+
+def test_adjoint_refuses_what_it_does_not_differentiate():
+    from paper_1611_02445_amd._abi import LbmError
+    s, _ = I.sphere_pack((12, 12, 12), 0.55, 2.0, 3.5, seed=23)
+    for kw in (dict(model="mrt-qc"), dict(storage="f16s")):
+        lat = new_lattice(s, 0.8, 7, **kw)
+        lat.init()
+        with pytest.raises(LbmError, match="UNSUPPORTED"):
+            lat.adjoint_seed(lat.current_state(), lat.new_state(), lat.new_grad())
