@@ -279,18 +279,19 @@ def _time_calib_kind(lat, kind, torch, launches=200, warmup=10):
 def sweep_layouts(args, torch):
     """The paper's intra-tile layout study (Section 3.3, Eqs. 11-13; Table 5):
     the propagation-only kernel with the per-direction slot maps XYZ, XYZ +
-    zigzagNE, XYZ + YXZ and all three, against the read/write-only kernel, on
+    zigzagNE, XYZ + YXZ and all three, and a face-major order for 128-byte
+    lines, against the read/write-only kernel, on
     fully fluid boxes with bounce-back walls (the paper's 100^3 cavity, 25^3
     tiles, and a 256^3 one that no cache holds)."""
     from paper_1611_02445_amd.lattice import Lattice
-    names = {1: "rw only", 3: "XYZ", 4: "XYZ + zigzagNE", 5: "XYZ + YXZ", 6: "all three"}
+    names = {1: "rw only", 3: "XYZ", 4: "XYZ + zigzagNE", 5: "XYZ + YXZ", 6: "all three", 7: "face-major"}
     rows = []
     for n in (100, 256):
         for st in ("f64", "f32"):
             lat = Lattice(np.zeros((n, n, n), np.uint8), 0.7, periodic=0, storage=st, tiles_per_wg=args.tpw,
                           tile_order=args.order)
             lat.init()
-            for kind in (3, 4, 5, 6, 1):
+            for kind in (3, 4, 5, 6, 7, 1):
                 ms = _time_calib_kind(lat, kind, torch, launches=max(10, min(200, args.steps)),
                                       warmup=max(2, min(10, args.warmup)))
                 mf = lat.n_fluid / (ms / 1e3) / 1e6

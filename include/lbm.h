@@ -298,9 +298,12 @@ int lbm_adjoint_set(lbm_ctx *ctx, const double *dense_dev, void *adj);
  * orders the tile's nodes by the XYZ map (x + 4y + 16z), the YXZ map
  * (y + 4x + 16z) or the zigzagNE map; kind 3 uses XYZ for every direction,
  * kind 4 adds zigzagNE for NE and SE, kind 5 YXZ for E, W, ET, EB, NW, SW,
- * WT and WB, kind 6 both.  src and dst are read and written in that layout
+ * WT and WB, kind 6 both.  Kind 7 (not the paper's) is a face-major order for
+ * 128-byte lines: y + 4z + 16x for E and W, x + 4z + 16y for N, S, NE, NW,
+ * SW and SE, XYZ for the rest, so that each face a neighbour reads is one
+ * contiguous run.  src and dst are read and written in that layout
  * (not the library's state layout, except for kind 3, whose bytes equal it).
- * They need every kept tile entirely fluid (else LBM_E_UNSUPPORTED), where
+ * Kinds 3-7 need every kept tile entirely fluid (else LBM_E_UNSUPPORTED), where
  * the layouts occupy the same bytes as a state lattice.
  * src != dst, both state lattices of this context (else LBM_E_INVAL).
  * ------------------------------------------------------------------------ */

@@ -615,11 +615,11 @@ extern "C" int lbm_adjoint_final(lbm_ctx *c, const void *eta_1, void *lambda_0) 
 
 extern "C" int lbm_calib_step(lbm_ctx *c, int32_t kind, const void *src, void *dst) {
     CHECK_CTX(c);
-    if (kind < 1 || kind > 6) return fail(LBM_E_INVAL, "lbm_calib_step: kind must be 1 to 6");
+    if (kind < 1 || kind > 7) return fail(LBM_E_INVAL, "lbm_calib_step: kind must be 1 to 7");
     // the layout study addresses the plain 64-slot blocks, which coincide
     // with the lattice's own bytes only when every kept tile is full
     if (kind >= 3 && c->n_fluid != (int64_t)TILE * c->n_tiles)
-        return fail(LBM_E_UNSUPPORTED, "lbm_calib_step: kinds 3-6 need every kept tile entirely fluid");
+        return fail(LBM_E_UNSUPPORTED, "lbm_calib_step: kinds 3-7 need every kept tile entirely fluid");
     if (c->n_tiles > 0 && (!src || !dst || src == dst)) return fail(LBM_E_INVAL, "lbm_calib_step: bad lattices");
     return launched(launch_calib(c->L, kind, c->params.storage, src, dst), "lbm_calib_step");
 }

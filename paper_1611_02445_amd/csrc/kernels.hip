@@ -697,9 +697,18 @@ __global__ __launch_bounds__(512) void k_calib(KArgs a) {
 //   YXZ      y + 4x + 16z        for E, W, ET, EB, NW, SW, WT, WB  (LS bit 0)
 //   zigzagNE 2(x + 3y + [x = 3](3 - y)·4) + (z & 1) + 16(z & 2)
 //                                for NE, SE                        (LS bit 1)
+// LS = 4 is not the paper's: a face-major order for 128-byte lines, where the
+// face a neighbour reads is one contiguous run of 16 nodes: x slowest
+// (y + 4z + 16x) for E and W, y slowest (x + 4z + 16y) for N, S and the four
+// xy edge directions, XYZ (z slowest already) for the rest.
 // Only defined on tiles that are entirely fluid (the host checks), where the
 // plain and the runs layouts occupy the same bytes.
 __device__ __forceinline__ int layout_slot(int ls, int i, int x, int y, int z) {
+    if (ls == 4) {
+        if (i == 1 || i == 3) return y + 4 * z + 16 * x;
+        if (i == 2 || i == 4 || (i >= 7 && i <= 10)) return x + 4 * z + 16 * y;
+        return x + 4 * y + 16 * z;
+    }
     const bool yxz = (ls & 1) && (i == 1 || i == 3 || i == 8 || i == 9 || i == 11 || i == 12 || i == 13 || i == 14);
     const bool zig = (ls & 2) && (i == 7 || i == 10);
     if (yxz) return y + 4 * x + 16 * z;
@@ -1249,7 +1258,8 @@ static hipError_t calib_layout_s(const Launch &L, const KArgs &a, int ls) {
     case 0: return calib_layout_t<S, 0>(L, a);
     case 1: return calib_layout_t<S, 1>(L, a);
     case 2: return calib_layout_t<S, 2>(L, a);
-    default: return calib_layout_t<S, 3>(L, a);
+    case 3: return calib_layout_t<S, 3>(L, a);
+    default: return calib_layout_t<S, 4>(L, a);
     }
 }
 
@@ -1258,8 +1268,9 @@ hipError_t launch_calib(const Launch &L, int kind, int storage, const void *src,
     Phys P{};
     const KArgs a = make_args(L, P, src, dst);
     if (kind >= 3) {
-        // kinds 3..6: layout sets XYZ, XYZ+zigzagNE, XYZ+YXZ, all three
-        static constexpr int LS[4] = {0, 2, 1, 3};
+        // kinds 3..6: layout sets XYZ, XYZ+zigzagNE, XYZ+YXZ, all three;
+        // kind 7: face-major
+        static constexpr int LS[5] = {0, 2, 1, 3, 4};
         const int ls = LS[kind - 3];
         if (storage == LBM_F64) return calib_layout_s<double>(L, a, ls);
         if (storage == LBM_F32) return calib_layout_s<float>(L, a, ls);

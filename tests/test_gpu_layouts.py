@@ -19,14 +19,23 @@ ZIG = [2 * (x + 3 * y + (4 if x == 3 else 0) * (3 - y)) + (z % 2) + 16 * (z & 2)
 # D3Q19 directions by name: E 1, W 3, NE 7, NW 8, SW 9, SE 10, ET 11, EB 12, WT 13, WB 14
 YXZ_DIRS = (1, 3, 11, 12, 8, 9, 13, 14)
 ZIG_DIRS = (7, 10)
-KINDS = {3: (False, False), 4: (False, True), 5: (True, False), 6: (True, True)}
+KINDS = {3: (False, False), 4: (False, True), 5: (True, False), 6: (True, True), 7: "face"}
+# the face-major order (kind 7): x slowest, y slowest
+XSLOW = [y + 4 * z + 16 * x for z in range(4) for y in range(4) for x in range(4)]
+YSLOW = [x + 4 * z + 16 * y for z in range(4) for y in range(4) for x in range(4)]
 DT = {"f64": "float64", "f32": "float32", "f16s": "float16"}
 
 
 def _slot_maps(kind):
     """maps[i][n] = slot of node n (x + 4y + 16z) in direction i's block."""
-    yxz, zig = KINDS[kind]
     maps = np.array([XYZ] * 19)
+    if KINDS[kind] == "face":
+        for i in (1, 3):  # E, W
+            maps[i] = XSLOW
+        for i in (2, 4, 7, 8, 9, 10):  # N, S and the xy edges
+            maps[i] = YSLOW
+        return maps
+    yxz, zig = KINDS[kind]
     for i in range(19):
         if yxz and i in YXZ_DIRS:
             maps[i] = YXZ
@@ -41,8 +50,13 @@ def _blocks(buf, lat, storage):
 
 
 def test_maps_are_permutations():
-    for m in (XYZ, YXZ, ZIG):
+    for m in (XYZ, YXZ, ZIG, XSLOW, YSLOW):
         assert sorted(m) == list(range(64))
+    # under the face-major order the x = 3 face (read by the east neighbour
+    # for E) and the y = 3 face (read by the north neighbour for N) are the
+    # last 16 slots: one 128-byte line in FP64
+    assert sorted(XSLOW[3 + 4 * y + 16 * z] for y in range(4) for z in range(4)) == list(range(48, 64))
+    assert sorted(YSLOW[x + 12 + 16 * z] for x in range(4) for z in range(4)) == list(range(48, 64))
     # zigzagNE keeps the two z-neighbours z = 2k, 2k+1 of a column side by side
     for x in range(4):
         for y in range(4):
@@ -68,7 +82,7 @@ def test_layout_kinds_conjugate_the_propagation(storage, periodic):
         assert np.array_equal(lat.get_state(b3).cpu().numpy(), O.pull(f0, solid, periodic=periodic))
     ref = _blocks(b3, lat, storage).cpu().numpy()
     src = _blocks(a, lat, storage).cpu().numpy()
-    for kind in (4, 5, 6):
+    for kind in (4, 5, 6, 7):
         maps = _slot_maps(kind)
         a_l = lat.new_state()
         out = lat.new_state()
@@ -94,3 +108,5 @@ def test_layout_kinds_need_full_tiles():
         lat.calib_step(4, lat.current_state(), b)
     with pytest.raises(LbmError):
         lat.calib_step(7, lat.current_state(), b)
+    with pytest.raises(LbmError):
+        lat.calib_step(8, lat.current_state(), b)
