@@ -526,8 +526,9 @@ void oracle_macroscopic(const double *f, const uint8_t *solid, int32_t nx, int32
  *     eta_t         = J_t^T lambda_t,   J_t = dC/dg at g_t = S s_{t-1}
  *     dL/dF        += (dC/dF)^T lambda_t
  *     lambda_{t-1}  = S^T eta_t
- * and dL/ds_0 = lambda_0.  Provided for the two single-relaxation-time
- * models (quasi-compressible, Eq. 3 and 5; incompressible, Eq. 4 and 6). */
+ * and dL/ds_0 = lambda_0.  Provided for every model: the single-relaxation-
+ * time ones (quasi-compressible, Eq. 3 and 5; incompressible, Eq. 4 and 6)
+ * and the multiple-relaxation-time operator with either equilibrium. */
 
 /* S as an operator on a whole field: g = S s (solid nodes of g set to 0) */
 void oracle_pull(const double *s, double *g, const uint8_t *solid, int32_t nx, int32_t ny, int32_t nz,
@@ -588,8 +589,58 @@ void oracle_pull_transpose(const double *mu, double *out, const uint8_t *solid, 
  * both:
  *   dS_i/du     = (1 - 1/(2tau)) w_i (9 (c_i.F) c_i - 3 F)
  *   dS_i/dF|_u  = (1 - 1/(2tau)) w_i (3 (c_i - u) + 9 (c_i.u) c_i) */
+/* the same for the multiple-relaxation-time operator (models 2 and 3):
+ *   f* = f - R (f - feq) + (I - R/2) G,   R = M^-1 S M,
+ *   G_i = w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)]  (the raw Guo source)
+ * so with mu = R^T lam and nu = (I - R/2)^T lam
+ *   (J^T lam)_j = lam_j - mu_j + sum_i mu_i dfeq_i/dg_j + sum_i nu_i dG_i/dg_j
+ *   (dC/dF)^T lam = sum_i mu_i dfeq_i/du du/dF + sum_i nu_i (dG_i/dF|_u + dG_i/du du/dF)
+ * with dG_i/du = w_i (9 (c_i.F) c_i - 3 F), dG_i/dF|_u = w_i (3 (c_i - u) + 9 (c_i.u) c_i)
+ * and feq, u of the model's equilibrium (Eq. 3, 5 or Eq. 4, 6). */
+static void collide_jt_mrt(int model, const double *fin, const double *F, double tau, const double *lam,
+                           double *eta, double *gF) {
+    const int inc = incompressible(model);
+    double s[Q], R[Q][Q], mu[Q], nu[Q], rho, u[3];
+    mrt_rates(tau, s);
+    for (int i = 0; i < Q; ++i)
+        for (int j = 0; j < Q; ++j) {
+            R[i][j] = 0.0;
+            for (int k = 0; k < Q; ++k) R[i][j] += MRT_MINV[i][k] * s[k] * MRT_M[k][j];
+        }
+    for (int j = 0; j < Q; ++j) {
+        mu[j] = 0.0;
+        for (int i = 0; i < Q; ++i) mu[j] += R[i][j] * lam[i];
+        nu[j] = lam[j] - 0.5 * mu[j];
+    }
+    moments(model, fin, F, &rho, u);
+    double A = 0.0, V[3] = {0.0, 0.0, 0.0}, D[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        double c[3] = {(double)CV[i][0], (double)CV[i][1], (double)CV[i][2]};
+        double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+        double cF = c[0] * F[0] + c[1] * F[1] + c[2] * F[2];
+        double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        A += mu[i] * (inc ? WT(i) : WT(i) * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+        for (int a = 0; a < 3; ++a) {
+            double dfeq_du = WT(i) * (inc ? 1.0 : rho) * (3.0 * c[a] + 9.0 * cu * c[a] - 3.0 * u[a]);
+            double dG_du = WT(i) * (9.0 * cF * c[a] - 3.0 * F[a]);
+            V[a] += mu[i] * dfeq_du + nu[i] * dG_du;
+            D[a] += nu[i] * WT(i) * (3.0 * (c[a] - u[a]) + 9.0 * cu * c[a]);
+        }
+    }
+    for (int j = 0; j < Q; ++j) {
+        double cj_u = 0.0;
+        for (int a = 0; a < 3; ++a) cj_u += V[a] * (inc ? CV[j][a] : (CV[j][a] - u[a]) / rho);
+        eta[j] = lam[j] - mu[j] + A + cj_u;
+    }
+    for (int a = 0; a < 3; ++a) gF[a] = V[a] / (inc ? 2.0 : 2.0 * rho) + D[a];
+}
+
 void oracle_collide_jt_node(int32_t model, const double *fin, const double *F, double tau, const double *lam,
                             double *eta, double *gF) {
+    if (multi_relaxation(model)) {
+        collide_jt_mrt(model, fin, F, tau, lam, eta, gF);
+        return;
+    }
     const int inc = model == 1;
     double rho, u[3];
     moments(model, fin, F, &rho, u);
@@ -618,11 +669,11 @@ void oracle_collide_jt_node(int32_t model, const double *fin, const double *F, d
 }
 
 /* loss L = (1/N_f) sum_fluid u_x(s) with u_x = (sum c_x s - F_x/2)/rho
- * (model 0) or sum c_x s - F_x/2 (model 1).  When lam != NULL also returns
- * dL/ds in lam[19][N] and adds dL/dF_x to gF. */
+ * (models 0, 2) or sum c_x s - F_x/2 (models 1, 3).  When lam != NULL also
+ * returns dL/ds in lam[19][N] and adds dL/dF_x to gF. */
 double oracle_loss_ux(int32_t model, const double *s, const uint8_t *solid, int32_t nx, int32_t ny, int32_t nz,
                       const double *force, double *lam, double *gF) {
-    const int inc = model == 1;
+    const int inc = incompressible(model);
     long N = (long)nx * ny * nz, nf = 0;
     for (long n = 0; n < N; ++n) nf += !solid[n];
     double L = 0.0;
