@@ -249,14 +249,13 @@ int lbm_tiles_to_dense(lbm_ctx *ctx, const void *tile_buf, int32_t ncomp, int32_
 /* ------------------------------------------------------------------------
  * Discrete adjoint of the fused step (an addition: the paper has no adjoint;
  * the forward operator is the one of Alg. 2 with Eq. 2, 3, 5, 7 and Guo
- * forcing).  Both LBGK models (quasi-compressible, Eq. 3 and 5;
- * incompressible, Eq. 4 and 6); FP64 storage with FP64 arithmetic, or FP32
- * storage with FP32 arithmetic.  FP16 storage, the multiple-relaxation-time
- * models and open boundaries return LBM_E_UNSUPPORTED; NULL buffers return
- * LBM_E_INVAL.
+ * forcing).  Every model (LBGK and LBMRT, quasi-compressible Eq. 3 and 5 or
+ * incompressible Eq. 4 and 6); FP64 storage with FP64 arithmetic, or FP32
+ * storage with FP32 arithmetic.  FP16 storage and open boundaries return
+ * LBM_E_UNSUPPORTED; NULL buffers return LBM_E_INVAL.
  *
  * Forward: s_t = C(S s_{t-1}, F), S = pull streaming with bounce-back,
- * C = local LBGK + Guo collision.  Loss L = (1/N_fluid) sum_fluid u_x(s_T),
+ * C = the model's local collision with Guo forcing.  Loss L = (1/N_fluid) sum_fluid u_x(s_T),
  * u_x from the stored lattice as lbm_macroscopic defines it for the model.
  * The adjoint lattices hold eta_t = J_t^T lambda_t (J_t = dC/dg at
  * g_t = S s_{t-1}, lambda_t = dL/ds_t); lambda_{t-1} = S^T eta_t is formed

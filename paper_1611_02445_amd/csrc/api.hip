@@ -554,8 +554,6 @@ extern "C" int lbm_tiles_to_dense(lbm_ctx *c, const void *tile_buf, int32_t ncom
 
 static int adjoint_supported(lbm_ctx *c) {
     if (c->params.storage == LBM_F16S) return fail(LBM_E_UNSUPPORTED, "adjoint: built for FP64 and FP32 storage only");
-    if (c->params.model != LBM_QUASI_COMPRESSIBLE && c->params.model != LBM_INCOMPRESSIBLE)
-        return fail(LBM_E_UNSUPPORTED, "adjoint: built for the single-relaxation-time (LBGK) models only");
     if (c->P.bc) return fail(LBM_E_UNSUPPORTED, "adjoint: not built for open boundaries");
     return LBM_OK;
 }

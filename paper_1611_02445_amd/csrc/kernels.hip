@@ -984,9 +984,8 @@ __global__ __launch_bounds__(512) void k_tiles_to_dense(KArgs a, const T *in, in
 }
 
 // ---------------------------------------------------------------------------
-// discrete adjoint (single-relaxation-time models, runs layout; FP64 storage
-// with FP64 arithmetic or FP32 storage with FP32 arithmetic, gradient sums in
-// FP64)
+// discrete adjoint (every model, runs layout; FP64 storage with FP64
+// arithmetic or FP32 storage with FP32 arithmetic, gradient sums in FP64)
 //
 // For the quasi-compressible collision C(g, F) with rho = sum g,
 // u = (sum c g + F/2)/rho (Eq. 3, 5):
@@ -1067,6 +1066,92 @@ __device__ __forceinline__ void collide_jt(const T (&d)[Q], T rho_base, const T 
     gz = T(0.5) * Vz * ir + kg * (rz - T(3) * q * uz);
 }
 
+// The same for the multiple-relaxation-time operator
+//   f* = f - R (f - feq) + (I - R/2) G,   R = M^-1 S M,
+// G_i = w_i (3 (c_i - u).F + 9 (c_i.u)(c_i.F)).  With M^-1 = M^T diag(1/|row|^2)
+// R = M^T diag(s/|row|^2) M is symmetric, so mu = R^T lam is the forward
+// relaxation applied to lam, and with nu = lam - mu/2
+//   (J^T lam)_j = lam_j - mu_j + A + V.(c_j - u)/rho   (incompressible: V.c_j)
+//   A = sum_i mu_i dfeq_i/drho,  V = sum_i [mu_i dfeq_i/du + nu_i w_i (9 (c_i.F) c_i - 3 F)]
+//   (dC/dF)^T lam = V/(2 rho) (incompressible V/2) + sum_i nu_i w_i (3 (c_i - u) + 9 (c_i.u) c_i)
+template <typename T, int INC>
+__device__ __forceinline__ void collide_jt_mrt(const T (&d)[Q], T rho_base, const T (&lam)[Q], T omega, T Fx, T Fy,
+                                               T Fz, T (&eta)[Q], T &gx, T &gy, T &gz) {
+    T drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        drho += d[i];
+        jx += T(CX[i]) * d[i];
+        jy += T(CY[i]) * d[i];
+        jz += T(CZ[i]) * d[i];
+    }
+    const T rho = rho_base + drho;
+    T ir = T(1);
+    if constexpr (!INC) ir = T(1) / rho;
+    const T ux = (jx + T(0.5) * Fx) * ir, uy = (jy + T(0.5) * Fy) * ir, uz = (jz + T(0.5) * Fz) * ir;
+    const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
+    const T bs = INC ? T(1) : rho;
+    T mk[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        mk[k] = T(0);
+        if (mrt_rate(k) == 0.0) continue;
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            if (MRT.c[k][i]) acc += T(MRT.c[k][i]) * lam[i];
+        const T rate = mrt_rate(k) < 0.0 ? omega : T(mrt_rate(k));
+        mk[k] = acc * (rate * T(1.0 / MRT.n[k]));
+    }
+    // P = sum (3a + 9a c.u + 9b c.F) c and Pd = sum (3b + 9b c.u) c with
+    // a = mu w bs, b = nu w; Sa = sum a, Sb = sum b
+    T A = 0, Sa = 0, Sb = 0, px = 0, py = 0, pz = 0, qx = 0, qy = 0, qz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T mu = T(0);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+            if (mrt_rate(k) != 0.0 && MRT.c[k][i]) mu += T(MRT.c[k][i]) * mk[k];
+        const T nu = lam[i] - T(0.5) * mu;
+        const T w = T(weight(i));
+        const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
+        const T cF = T(CX[i]) * Fx + T(CY[i]) * Fy + T(CZ[i]) * Fz;
+        A += INC ? mu * w : mu * w * (T(1) + T(3) * cu + T(4.5) * cu * cu - usq);
+        const T a = mu * w * bs, b = nu * w;
+        Sa += a;
+        Sb += b;
+        const T pc = T(3) * a + T(9) * a * cu + T(9) * b * cF;
+        const T qc = T(3) * b + T(9) * b * cu;
+        if (CX[i]) { px += T(CX[i]) * pc; qx += T(CX[i]) * qc; }
+        if (CY[i]) { py += T(CY[i]) * pc; qy += T(CY[i]) * qc; }
+        if (CZ[i]) { pz += T(CZ[i]) * pc; qz += T(CZ[i]) * qc; }
+        eta[i] = lam[i] - mu;
+    }
+    const T Vx = px - T(3) * (ux * Sa + Fx * Sb);
+    const T Vy = py - T(3) * (uy * Sa + Fy * Sb);
+    const T Vz = pz - T(3) * (uz * Sa + Fz * Sb);
+    const T Vu = Vx * ux + Vy * uy + Vz * uz;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const T Vc = T(CX[j]) * Vx + T(CY[j]) * Vy + T(CZ[j]) * Vz;
+        if constexpr (INC) eta[j] += A + Vc;
+        else eta[j] += A + (Vc - Vu) * ir;
+    }
+    gx = T(0.5) * Vx * ir + (qx - T(3) * ux * Sb);
+    gy = T(0.5) * Vy * ir + (qy - T(3) * uy * Sb);
+    gz = T(0.5) * Vz * ir + (qz - T(3) * uz * Sb);
+}
+
+// the transposed Jacobian of a model's collision
+template <typename T, int MODEL>
+__device__ __forceinline__ void collide_jt_model(const T (&d)[Q], T rho_base, const T (&lam)[Q], T omega, T kg, T Fx,
+                                                 T Fy, T Fz, T (&eta)[Q], T &gx, T &gy, T &gz) {
+    if constexpr (MODEL >= LBM_MRT_QUASI_COMPRESSIBLE)
+        collide_jt_mrt<T, (MODEL & 1)>(d, rho_base, lam, omega, Fx, Fy, Fz, eta, gx, gy, gz);
+    else
+        collide_jt<T, (MODEL & 1)>(d, rho_base, lam, omega, kg, Fx, Fy, Fz, eta, gx, gy, gz);
+}
+
 struct AdjArgs {
     const char *s;      // forward lattice feeding the forward gather
     const char *eta_in; // adjoint lattice feeding the reverse gather
@@ -1085,7 +1170,7 @@ struct AdjArgs {
 // u_x = sum c_x s - F_x/2 (incompressible) it is c_x / N_fluid.
 template <int ST, int MODEL, typename OffT>
 __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
-    constexpr int INC = MODEL == LBM_INCOMPRESSIBLE;
+    constexpr int INC = MODEL & 1;
     using T = typename Codec<ST>::S;
     const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
@@ -1112,7 +1197,7 @@ __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
             T s[Q];
 #pragma unroll
             for (int i = 0; i < Q; ++i) s[i] = g[i];
-            collide<T, LBM_QUASI_COMPRESSIBLE>(s, rb, om, kg, Fx, Fy, Fz);
+            collide_model<T, MODEL>(s, rb, om, kg, Fx, Fy, Fz);
             T drT = 0, jx = 0;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
@@ -1124,7 +1209,7 @@ __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) lam[i] = (T(CX[i]) - uxT) * irT * inv_n;
         }
-        collide_jt<T, INC>(g, rb, lam, om, kg, Fx, Fy, Fz, eta, gx, gy, gz);
+        collide_jt_model<T, MODEL>(g, rb, lam, om, kg, Fx, Fy, Fz, eta, gx, gy, gz);
         gx += T(-0.5) * irT * inv_n;
     }
     store_tile<T, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
@@ -1155,8 +1240,7 @@ __global__ __launch_bounds__(512) void k_adj_step(AdjArgs a) {
         T Fx, Fy, Fz;
         load_force<T>(a.P, t, lane, Fx, Fy, Fz);
         T gx, gy, gz;
-        collide_jt<T, MODEL == LBM_INCOMPRESSIBLE>(g, T(a.P.rho_base), lam, T(a.P.omega), T(a.P.kg), Fx, Fy, Fz, eta,
-                                                   gx, gy, gz);
+        collide_jt_model<T, MODEL>(g, T(a.P.rho_base), lam, T(a.P.omega), T(a.P.kg), Fx, Fy, Fz, eta, gx, gy, gz);
         double *go = a.grad + (size_t)t * 3 * TILE + lane;
         go[0] += a.P.rho0 * (double)gx;
         go[TILE] += a.P.rho0 * (double)gy;
@@ -1380,8 +1464,8 @@ static AdjArgs make_adj(const Launch &L, const Phys &P, const void *s, const voi
     return a;
 }
 
-// the adjoint kernels exist for FP64 and FP32 storage (runs layout) and the
-// two single-relaxation-time models; the final reverse gather has no model
+// the adjoint kernels exist for FP64 and FP32 storage (runs layout) and every
+// model; the final reverse gather has no model
 template <int ST, int MODEL, typename OffT>
 struct SeedK {
     static constexpr auto fn = k_adj_seed<ST, MODEL, OffT>;
@@ -1405,8 +1489,14 @@ template <template <int, int, typename> class K>
 static hipError_t launch_adj(const Launch &L, const AdjArgs &a) {
     if (L.n_tiles == 0) return hipSuccess;
     const bool f32 = a.P.storage == LBM_F32;
-    void (*fn)(AdjArgs) = a.P.model == LBM_INCOMPRESSIBLE ? adj_fn<K, LBM_INCOMPRESSIBLE>(L, f32)
-                                                            : adj_fn<K, LBM_QUASI_COMPRESSIBLE>(L, f32);
+    void (*fn)(AdjArgs) = nullptr;
+    switch (a.P.model) {
+    case LBM_QUASI_COMPRESSIBLE: fn = adj_fn<K, LBM_QUASI_COMPRESSIBLE>(L, f32); break;
+    case LBM_INCOMPRESSIBLE: fn = adj_fn<K, LBM_INCOMPRESSIBLE>(L, f32); break;
+    case LBM_MRT_QUASI_COMPRESSIBLE: fn = adj_fn<K, LBM_MRT_QUASI_COMPRESSIBLE>(L, f32); break;
+    case LBM_MRT_INCOMPRESSIBLE: fn = adj_fn<K, LBM_MRT_INCOMPRESSIBLE>(L, f32); break;
+    default: return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL(fn, dim3(L.grid), block_of(L), 0, L.stream, a);
     return hipGetLastError();
 }
