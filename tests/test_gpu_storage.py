@@ -8,8 +8,8 @@ d_i = f_i - w_i rho0 (|d_i| ~ 1e-3..1e-2 here), rounded once per step:
   FP16: h = fp16(2^k d) has an 11-bit significand: the error per step is
         below one ulp, 2^-10 * |d| (stochastic rounding, the default) or half
         an ulp (nearest-even), i.e. ~1e-6 here.
-The benchmark spec's target for both is |k - k_64| / k_64 <= 1e-3 on the
-permeability; velocity errors are reported."""
+The target for both is |k - k_64| / k_64 <= 1e-3 on the permeability;
+velocity errors are reported."""
 import numpy as np
 import pytest
 
