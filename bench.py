@@ -177,6 +177,30 @@ def time_adjoint(args, torch):
     out["adjoint_hbm_frac"] = round(out["bytes_per_fluid_update_adjoint"] * nf / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     log(f"[bench] adjoint: {out['MFLUPS_adjoint_kernels']} MFLUPS kernels, "
         f"{out['MFLUPS_backward_incl_recompute']} MFLUPS incl. recompute")
+    del run, lat
+    # the adjoint kernels of the other collision models on the same pack
+    # (200 reverse steps over one recomputed state each)
+    other = {}
+    for model in ("inc", "mrt-qc", "mrt-inc"):
+        lm = Lattice(solid, 0.8, periodic=7, model=model, tiles_per_wg=args.tpw, tile_order=args.order)
+        lm.set_force(g.cuda())
+        lm.init()
+        s_buf, e_in, e_out, grad = lm.current_state(), lm.new_adjoint(), lm.new_adjoint(), lm.new_grad()
+        lm.adjoint_seed(s_buf, e_in, grad)
+        for _ in range(10):
+            lm.adjoint_step(s_buf, e_in, e_out, grad)
+            e_in, e_out = e_out, e_in
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lm.stream)
+        for _ in range(200):
+            lm.adjoint_step(s_buf, e_in, e_out, grad)
+            e_in, e_out = e_out, e_in
+        e1.record(lm.stream)
+        torch.cuda.synchronize()
+        other[model] = round(lm.n_fluid * 200 / (e0.elapsed_time(e1) / 1e3) / 1e6, 1)
+        del lm, e_in, e_out, grad
+    out["MFLUPS_adjoint_step_other_models"] = other
+    log(f"[bench] adjoint step, other models: {other}")
     return out
 
 

@@ -100,7 +100,8 @@ def test_autograd_function():
     assert np.max(np.abs(g_t.grad.cpu().numpy()[:, fl] - 3 * gF_o[:, fl])) <= 1e-11 * 3 * np.abs(gF_o).max()
 
 
-def test_adjoint_full_size_finite_differences():
+@pytest.mark.parametrize("model", ["qc", "mrt-qc"])
+def test_adjoint_full_size_finite_differences(model):
     """128^3 periodic sphere pack, porosity 0.5, radius U[4,12), tau 0.8,
     T = 2000, checkpoints every 100 steps, per-node g_x ~ N(1e-6, 1e-7).
     Central differences of the GPU forward: g_x at 32 random fluid nodes,
@@ -114,8 +115,8 @@ def test_adjoint_full_size_finite_differences():
     g = np.zeros((3,) + sp.shape)
     g[0] = rng.normal(1e-6, 1e-7, sp.shape)
     g[:, sp == 1] = 0.0
-    log(f"[case] adjoint 128^3 spheres={n_sph} T={T} K={K}")
-    lat = new_lattice(s, tau, 7)
+    log(f"[case] adjoint 128^3 spheres={n_sph} T={T} K={K} model={model}")
+    lat = new_lattice(s, tau, 7, model=model)
     lat.init()
     f0 = lat.get_state()
     g_t = torch.from_numpy(g).cuda()
