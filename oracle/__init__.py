@@ -132,8 +132,10 @@ def collide_mrt_rates(fin, F, s, model=2):
 
 
 def zou_he(f, btype, u_in=(0.0, 0.0, 0.0), rho_out=1.0, F=(0.0, 0.0, 0.0), model=0):
-    """The populations of one node after the open-boundary rebuild
-    (btype 1 velocity inlet, 2 pressure outlet)."""
+    """The populations of one node after the open-boundary rebuild.  btype
+    1..12: axis (btype-1)//4; (btype-1)%4 = 0 velocity node with unknowns
+    c_a = +1, 1 pressure node c_a = -1, 2 velocity c_a = -1, 3 pressure
+    c_a = +1 (1 and 2: the x inlet and outlet)."""
     out = _f64(f).copy()
     lib().oracle_zou_he(int(btype), int(model), _p(_f64(u_in)), float(rho_out), _p(_f64(F)), _p(out))
     return out
@@ -141,7 +143,7 @@ def zou_he(f, btype, u_in=(0.0, 0.0, 0.0), rho_out=1.0, F=(0.0, 0.0, 0.0), model
 
 def run_bc(f, solid, tau, nsteps, btype, u_in=(0.0, 0.0, 0.0), rho_out=1.0, force=None, periodic=0, model=0):
     """nsteps steps with open boundaries: btype [nz,ny,nx] uint8 (0 none,
-    1 velocity inlet u_in, 2 pressure outlet rho_out)."""
+    else a code of zou_he: velocity nodes get u_in, pressure nodes rho_out)."""
     solid = _u8(solid)
     nz, ny, nx = solid.shape
     fa = _f64(f).copy()

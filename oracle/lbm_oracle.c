@@ -27,7 +27,8 @@
  *     kernels (Section 2.2; no matrix given): the D3Q19 moment basis and
  *     relaxation rates of d'Humieres et al. (2002), both equilibria,
  *   - the Zou-He velocity inlet and constant-pressure outlet the paper
- *     names for its open boundaries (Section 2.2), on faces normal to x.
+ *     names for its open boundaries (Section 2.2), on faces normal to any
+ *     axis.
  *
  * Parity unpinned: the rates of the moments eps, q, pi and m (1.4, 1.2,
  * 1.4, 1.98).  They act below the Navier-Stokes level, so no transport
@@ -336,57 +337,63 @@ static void gather(const box_t *b, const double *s, long N, int x, int y, int z,
 
 /* ------------------------------------------------------------------ */
 /* open boundaries (the paper's Zou-He velocity inlet and constant-     */
-/* pressure outlet, Section 2.2) on faces normal to x: after the gather, */
-/* the populations that enter through the face are rebuilt so that the   */
-/* node has the prescribed velocity (inlet) or density (outlet).          */
-/* Types: 1 = velocity inlet, the domain lies at +x (unknown: c_x = +1); */
-/* 2 = pressure outlet, the domain lies at -x (unknown: c_x = -1).       */
+/* pressure outlet, Section 2.2) on faces normal to an axis: after the   */
+/* gather, the populations that enter through the face are rebuilt so    */
+/* that the node has the prescribed velocity (velocity node) or density  */
+/* (pressure node).                                                       */
+/* Code c = 1..12: axis a = (c-1)/4 (x, y, z); r = (c-1)%4 gives the kind */
+/* and the sign n = c_a of the unknown populations:                       */
+/*   r = 0 velocity, n = +1 (the domain lies at +a: an inlet on the low   */
+/*         face); r = 1 pressure, n = -1 (an outlet on the high face);    */
+/*   r = 2 velocity, n = -1;  r = 3 pressure, n = +1.                     */
+/* Codes 1 and 2 are the x inlet and x outlet.                            */
 /* With a body force the rebuilt momentum is J = rho u - F/2, so that    */
-/* the collision's velocity (J + F/2)/rho is the prescribed one; the     */
-/* outlet's tangential velocity is 0.                                     */
-/* Unknown i (c_ix = n) from its opposite, Zou and He's bounce-back of   */
+/* the collision's velocity (J + F/2)/rho is the prescribed one; a        */
+/* pressure node's tangential velocity is 0.                              */
+/* Unknown i (c_ia = n) from its opposite, Zou and He's bounce-back of   */
 /* the non-equilibrium part with the tangential-momentum correction of   */
 /* Hecht and Harting (2010):                                              */
-/*   f_i = f_opp(i) + 6 w_i (c_i . J) - sum_t c_it N_t,                  */
-/*   N_t = 1/2 sum_{c_x = 0} c_t f - J_t / 3   (t = y, z)                */
+/*   f_i = f_opp(i) + 6 w_i (c_i . J) - sum_{t != a} c_it N_t,           */
+/*   N_t = 1/2 sum_{c_a = 0} c_t f - J_t / 3                             */
 /* ------------------------------------------------------------------ */
 typedef struct {
-    const uint8_t *type; /* [N] 0 none, 1 inlet, 2 outlet; NULL = no open boundaries */
-    double u[3];         /* inlet velocity */
-    double rho_out;      /* outlet density */
+    const uint8_t *type; /* [N] 0 none, else a code 1..12; NULL = no open boundaries */
+    double u[3];         /* velocity of the velocity nodes */
+    double rho_out;      /* density of the pressure nodes */
 } bc_t;
 
-static void zou_he(int type, int model, const double u_in[3], double rho_out, const double F[3], double f[Q]) {
-    const int n = (type == 1) ? 1 : -1; /* c_x of the unknown populations */
-    double s_tan = 0.0, s_in = 0.0, t[3] = {0.0, 0.0, 0.0};
+static void zou_he(int code, int model, const double u_in[3], double rho_out, const double F[3], double f[Q]) {
+    const int a = (code - 1) / 4, r = (code - 1) % 4;
+    const int velocity = (r == 0 || r == 2);
+    const int n = (r == 0 || r == 3) ? 1 : -1; /* c_a of the unknown populations */
+    double s_tan = 0.0, s_known = 0.0, t[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < Q; ++i) {
-        if (CV[i][0] == 0) {
+        if (CV[i][a] == 0) {
             s_tan += f[i];
-            t[1] += CV[i][1] * f[i];
-            t[2] += CV[i][2] * f[i];
-        } else if (CV[i][0] == -n) {
-            s_in += f[i]; /* the populations leaving through the face, known */
+            for (int b = 0; b < 3; ++b) t[b] += CV[i][b] * f[i];
+        } else if (CV[i][a] == -n) {
+            s_known += f[i]; /* the populations leaving through the face */
         }
     }
     double J[3];
-    if (type == 1) {
+    if (velocity) {
         if (!incompressible(model)) {
-            const double rho = (s_tan + 2.0 * s_in - 0.5 * n * F[0]) / (1.0 - n * u_in[0]);
-            for (int a = 0; a < 3; ++a) J[a] = rho * u_in[a] - 0.5 * F[a];
+            const double rho = (s_tan + 2.0 * s_known - 0.5 * n * F[a]) / (1.0 - n * u_in[a]);
+            for (int b = 0; b < 3; ++b) J[b] = rho * u_in[b] - 0.5 * F[b];
         } else {
-            for (int a = 0; a < 3; ++a) J[a] = u_in[a] - 0.5 * F[a];
+            for (int b = 0; b < 3; ++b) J[b] = u_in[b] - 0.5 * F[b];
         }
     } else {
-        /* sum f = rho_out and sum c_x f = J_x fix the normal momentum */
-        J[0] = n * (rho_out - s_tan - 2.0 * s_in);
-        J[1] = -0.5 * F[1];
-        J[2] = -0.5 * F[2];
+        /* sum f = rho_out and sum c_a f = J_a fix the normal momentum */
+        for (int b = 0; b < 3; ++b) J[b] = -0.5 * F[b];
+        J[a] = n * (rho_out - s_tan - 2.0 * s_known);
     }
-    const double N1 = 0.5 * t[1] - J[1] / 3.0, N2 = 0.5 * t[2] - J[2] / 3.0;
+    double N[3];
+    for (int b = 0; b < 3; ++b) N[b] = (b == a) ? 0.0 : 0.5 * t[b] - J[b] / 3.0;
     for (int i = 0; i < Q; ++i) {
-        if (CV[i][0] != n) continue;
+        if (CV[i][a] != n) continue;
         const double cJ = CV[i][0] * J[0] + CV[i][1] * J[1] + CV[i][2] * J[2];
-        f[i] = f[OPP(i)] + 6.0 * WT(i) * cJ - CV[i][1] * N1 - CV[i][2] * N2;
+        f[i] = f[OPP(i)] + 6.0 * WT(i) * cJ - CV[i][0] * N[0] - CV[i][1] * N[1] - CV[i][2] * N[2];
     }
 }
 

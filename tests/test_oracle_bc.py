@@ -19,15 +19,26 @@ def _random_node(seed):
     return w * (1.0 + 0.05 * rng.uniform(-1, 1, 19)), rng
 
 
+def _code(axis, kind, n):
+    """the rebuild code of a face: kind 'v' (velocity) or 'p' (pressure),
+    n = c_axis of the unknown populations"""
+    r = {("v", 1): 0, ("p", -1): 1, ("v", -1): 2, ("p", 1): 3}[(kind, n)]
+    return 1 + 4 * axis + r
+
+
+FACES = [(a, n) for a in range(3) for n in (1, -1)]
+
+
 @pytest.mark.parametrize("model", [0, 1])
-def test_inlet_rebuild_gives_the_prescribed_velocity(model):
+@pytest.mark.parametrize("axis,n", FACES)
+def test_inlet_rebuild_gives_the_prescribed_velocity(model, axis, n):
     c, _, _ = O.lattice()
     for seed in range(6):
         f, rng = _random_node(seed)
         u_in = rng.normal(0, 0.02, 3)
         F = rng.normal(0, 1e-4, 3)
-        g = O.zou_he(f, 1, u_in=u_in, F=F, model=model)
-        keep = c[:, 0] != 1
+        g = O.zou_he(f, _code(axis, "v", n), u_in=u_in, F=F, model=model)
+        keep = c[:, axis] != n
         assert np.array_equal(g[keep], f[keep])
         rho, j = g.sum(), c.T @ g
         u = (j + 0.5 * F) / (rho if model == 0 else 1.0)
@@ -35,18 +46,42 @@ def test_inlet_rebuild_gives_the_prescribed_velocity(model):
 
 
 @pytest.mark.parametrize("model", [0, 1])
-def test_outlet_rebuild_gives_the_prescribed_density(model):
+@pytest.mark.parametrize("axis,n", FACES)
+def test_outlet_rebuild_gives_the_prescribed_density(model, axis, n):
     c, _, _ = O.lattice()
+    tang = [b for b in range(3) if b != axis]
     for seed in range(6):
         f, rng = _random_node(10 + seed)
         rho_out = 1.0 + 0.01 * rng.uniform(-1, 1)
         F = rng.normal(0, 1e-4, 3)
-        g = O.zou_he(f, 2, rho_out=rho_out, F=F, model=model)
-        keep = c[:, 0] != -1
+        g = O.zou_he(f, _code(axis, "p", n), rho_out=rho_out, F=F, model=model)
+        keep = c[:, axis] != n
         assert np.array_equal(g[keep], f[keep])
         assert abs(g.sum() - rho_out) <= 1e-15
         j = c.T @ g
-        assert np.abs(j[1:] + 0.5 * F[1:]).max() <= 1e-16
+        assert np.abs(j[tang] + 0.5 * F[tang]).max() <= 1e-16
+
+
+def test_codes_one_and_two_are_the_x_inlet_and_outlet():
+    assert _code(0, "v", 1) == 1 and _code(0, "p", -1) == 2
+
+
+def test_rebuild_is_covariant_under_axis_relabelling():
+    """Rotating the lattice so that x goes to y maps the x-face rebuild to
+    the y-face rebuild: the codes differ only by the axis."""
+    c, _, _ = O.lattice()
+    # permutation of the velocities for (x, y, z) -> (y, z, x)
+    idx = {tuple(v): i for i, v in enumerate(c)}
+    perm = np.array([idx[(v[2], v[0], v[1])] for v in c])  # direction i -> its image
+    f, rng = _random_node(99)
+    u_in = rng.normal(0, 0.02, 3)
+    for kind, n in (("v", 1), ("p", -1), ("v", -1), ("p", 1)):
+        gx = O.zou_he(f, _code(0, kind, n), u_in=u_in, rho_out=1.003)
+        fy = np.empty(19)
+        fy[perm] = f
+        uy = np.array([u_in[2], u_in[0], u_in[1]])
+        gy = O.zou_he(fy, _code(1, kind, n), u_in=uy, rho_out=1.003)
+        assert np.abs(gy[perm] - gx).max() <= 1e-15
 
 
 def _channel(nx, H, nz):
