@@ -138,7 +138,7 @@ typedef struct lbm_sizes {
     size_t force_bytes;      /* per-node force field in tile order: n_tiles * 3 * 64 * sizeof(arith) */
     size_t adjoint_bytes;    /* one adjoint lattice: state_bytes (FP64, FP32), 0 for FP16 */
     size_t grad_force_bytes; /* force gradient, FP64: n_tiles * 3 * 64 * 8 */
-    size_t bc_bytes;         /* open-boundary masks: n_tiles * 2 * 8 */
+    size_t bc_bytes;         /* open boundaries: n_tiles * 72 (node mask + 64 node codes) */
     size_t dense_nodes;      /* nx * ny * nz of the padded box */
 } lbm_sizes;
 
@@ -177,18 +177,24 @@ int lbm_set_force(lbm_ctx *ctx, double gx, double gy, double gz, const double *g
                   void *g_tile_buf);
 
 /* Open boundaries (the paper's Zou-He velocity inlet and constant-pressure
- * outlet, Section 2.2) on faces normal to x.
- *   type_host  host [nz][ny][nx] bytes over the padded box: 0 none,
- *              1 velocity inlet (the domain lies at +x: the populations with
- *              c_x = +1 are rebuilt so that the node's velocity is u),
- *              2 pressure outlet (the domain lies at -x: the populations with
- *              c_x = -1 are rebuilt so that its density is rho_out and its
- *              tangential velocity 0); NULL removes all open boundaries
+ * outlet, Section 2.2) on faces normal to any axis.
+ *   type_host  host [nz][ny][nx] bytes over the padded box: 0 none, else a
+ *              code 1..12 with axis a = (code-1)/4 (0 x, 1 y, 2 z) and
+ *              r = (code-1)%4:
+ *                r = 0 velocity node, the populations with c_a = +1 are
+ *                      rebuilt (the domain lies at +a: an inlet on a low face),
+ *                r = 1 pressure node, c_a = -1 rebuilt (an outlet on a high face),
+ *                r = 2 velocity node, c_a = -1 rebuilt,
+ *                r = 3 pressure node, c_a = +1 rebuilt;
+ *              a velocity node gets velocity (ux, uy, uz), a pressure node
+ *              density rho_out and tangential velocity 0 (codes 1 and 2 are
+ *              the x inlet and outlet); NULL removes all open boundaries
  *   bc_tile_buf  device buffer of bc_bytes (caller-owned, must outlive its use)
  * The rebuild follows the gather (which bounces back at the missing
  * upstream nodes) and precedes the collision; with a body force it targets the
  * momentum rho u - F/2 so that the collision's velocity is the prescribed
- * one.  Flagged nodes must be fluid (else LBM_E_INVAL).  Synchronises. */
+ * one.  Flagged nodes must be fluid, codes at most 12 and every velocity
+ * component below 1 in magnitude (else LBM_E_INVAL).  Synchronises. */
 int lbm_set_boundaries(lbm_ctx *ctx, const uint8_t *type_host, double ux, double uy, double uz, double rho_out,
                        void *bc_tile_buf);
 

@@ -160,7 +160,7 @@ extern "C" int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *para
     // FP16 storage has no adjoint
     out->adjoint_bytes = params->storage == LBM_F16S ? 0 : out->state_bytes;
     out->grad_force_bytes = n * 3 * TILE * sizeof(double);
-    out->bc_bytes = n * 2 * sizeof(uint64_t);
+    out->bc_bytes = n * 9 * sizeof(uint64_t);
     out->dense_nodes = (size_t)tiles->nx * (size_t)tiles->ny * (size_t)tiles->nz;
     return LBM_OK;
 }
@@ -351,24 +351,27 @@ extern "C" int lbm_set_boundaries(lbm_ctx *c, const uint8_t *type_host, double u
     }
     if (!std::isfinite(ux) || !std::isfinite(uy) || !std::isfinite(uz) || !std::isfinite(rho_out) || !(rho_out > 0))
         return fail(LBM_E_INVAL, "lbm_set_boundaries: non-finite velocity or non-positive density");
-    if (!(ux < 1.0)) return fail(LBM_E_INVAL, "lbm_set_boundaries: inlet velocity u_x must be below 1");
+    if (!(std::fabs(ux) < 1.0 && std::fabs(uy) < 1.0 && std::fabs(uz) < 1.0))
+        return fail(LBM_E_INVAL, "lbm_set_boundaries: every velocity component must be below 1 in magnitude");
     if (c->n_tiles > 0 && !bc_tile_buf) return fail(LBM_E_INVAL, "lbm_set_boundaries: NULL tile buffer");
     const size_t nx = (size_t)c->nx, ny = (size_t)c->ny, nz = (size_t)c->nz;
     // every flagged node must be a fluid node of a kept tile
     size_t flagged = 0;
     for (size_t n = 0; n < nx * ny * nz; ++n) {
-        if (type_host[n] > 2) return fail(LBM_E_INVAL, "lbm_set_boundaries: node type %d is not 0, 1 or 2", type_host[n]);
+        if (type_host[n] > 12) return fail(LBM_E_INVAL, "lbm_set_boundaries: node code %d is not in 0..12", type_host[n]);
         flagged += type_host[n] != 0;
     }
-    std::vector<uint64_t> masks((size_t)c->n_tiles * 2, 0);
+    // per tile: the mask of its boundary nodes, then their 64 codes
+    std::vector<uint64_t> masks((size_t)c->n_tiles * 9, 0);
     size_t found = 0;
     for (int64_t d = 0; d < c->n_tiles; ++d) {
         const size_t x0 = (size_t)c->corner[3 * d], y0 = (size_t)c->corner[3 * d + 1], z0 = (size_t)c->corner[3 * d + 2];
+        uint8_t *codes = reinterpret_cast<uint8_t *>(&masks[9 * d + 1]);
         for (int lane = 0; lane < TILE; ++lane) {
             const size_t x = x0 + (lane & 3), y = y0 + ((lane >> 2) & 3), z = z0 + (lane >> 4);
             const uint8_t t = type_host[x + nx * (y + ny * z)];
-            if (t == 1) masks[2 * d] |= 1ull << lane;
-            if (t == 2) masks[2 * d + 1] |= 1ull << lane;
+            if (t) masks[9 * d] |= 1ull << lane;
+            codes[lane] = t;
             found += t != 0;
         }
     }
@@ -380,8 +383,7 @@ extern "C" int lbm_set_boundaries(lbm_ctx *c, const uint8_t *type_host, double u
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "lbm_set_boundaries: reading tile masks");
     for (int64_t d = 0; d < c->n_tiles; ++d)
-        if ((masks[2 * d] | masks[2 * d + 1]) & ~rec[d].mask)
-            return fail(LBM_E_INVAL, "lbm_set_boundaries: a flagged node is solid");
+        if (masks[9 * d] & ~rec[d].mask) return fail(LBM_E_INVAL, "lbm_set_boundaries: a flagged node is solid");
     if (c->n_tiles > 0) {
         e = hipMemcpyAsync(bc_tile_buf, masks.data(), masks.size() * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

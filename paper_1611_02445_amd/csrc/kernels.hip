@@ -525,59 +525,73 @@ __device__ __forceinline__ void collide_mrt(T (&d)[Q], T rho_base, T omega, T Fx
 
 // ---------------------------------------------------------------------------
 // open boundaries (the paper's Zou-He velocity inlet and constant-pressure
-// outlet) on faces normal to x.  After the gather, an inlet node rebuilds its
-// populations with c_x = +1, an outlet node those with c_x = -1, each from its
-// opposite:  f_i = f_opp(i) + 6 w_i (c_i . J) - c_iy N_y - c_iz N_z,
-// N_t = 1/2 sum_{c_x = 0} c_t f - J_t / 3 (tangential-momentum correction),
-// with J = rho u - F/2 (inlet: rho from the known populations and u_x) or
-// J_x from the outlet density and J_t = -F_t/2.  On shifted values the
-// rebuild is unchanged (opposite directions have equal weights); only the
-// density sums add rho_base times the weights of their sets (2/3 for
-// c_x = 0, 1/6 for either normal set).
+// outlet) on faces normal to an axis.  Each boundary node carries a code
+// 1..12: axis a = (code-1)/4, r = (code-1)%4: r = 0 velocity node whose
+// unknown populations have c_a = +1, 1 pressure node c_a = -1, 2 velocity
+// c_a = -1, 3 pressure c_a = +1.  After the gather, the unknown populations
+// are rebuilt from their opposites:
+//   f_i = f_opp(i) + 6 w_i (c_i . J) - sum_{t != a} c_it N_t,
+//   N_t = 1/2 sum_{c_a = 0} c_t f - J_t / 3   (tangential-momentum correction),
+// with J = rho u - F/2 (velocity node: rho from the known populations and
+// u_a) or J_a from the prescribed density and J_t = -F_t/2 (pressure node).
+// On shifted values the rebuild is unchanged (opposite directions have equal
+// weights); only the density sums add rho_base times the weights of their
+// sets (2/3 for c_a = 0, 1/6 for either normal set, for every axis).
+// Per tile the boundary buffer holds a mask of its boundary nodes and their
+// 64 codes: [n_tiles][9] uint64.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int axis_c(int a, int i) { return a == 0 ? CX[i] : (a == 1 ? CY[i] : CZ[i]); }
+
 template <typename T, int INC>
-__device__ __forceinline__ void open_boundary(T (&d)[Q], const Phys &P, int t, T Fx, T Fy, T Fz) {
-    const uint64_t in_m = P.bc[2 * (size_t)t], out_m = P.bc[2 * (size_t)t + 1];
-    if (!(in_m | out_m)) return;  // no boundary node in this tile
-    const bool is_in = lane_on(in_m), is_out = lane_on(out_m);
-    if (!(is_in || is_out)) return;
+__device__ __forceinline__ void open_boundary(T (&d)[Q], const Phys &P, int t, int lane, T Fx, T Fy, T Fz) {
+    const uint64_t *rec = P.bc + 9 * (size_t)t;
+    const uint64_t any = rec[0];
+    if (!any) return;  // no boundary node in this tile
+    if (!lane_on(any)) return;
+    const int code = (int)reinterpret_cast<const uint8_t *>(rec + 1)[lane];
+    const int a = (code - 1) >> 2, r = (code - 1) & 3;
+    const bool velocity = (r == 0 || r == 2);
+    const int n = (r == 0 || r == 3) ? 1 : -1;  // c_a of the unknown populations
     const T rb = T(P.rho_base);
-    T s_tan = 0, s_neg = 0, s_pos = 0, ty = 0, tz = 0;
+    T s_tan = 0, s_known = 0, tx = 0, ty = 0, tz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        if (CX[i] == 0) {
+        const int ca = axis_c(a, i);
+        if (ca == 0) {
             s_tan += d[i];
-            if (CY[i]) ty += CY[i] > 0 ? d[i] : -d[i];
-            if (CZ[i]) tz += CZ[i] > 0 ? d[i] : -d[i];
-        } else if (CX[i] < 0) {
-            s_neg += d[i];
-        } else {
-            s_pos += d[i];
+            tx += T(CX[i]) * d[i];
+            ty += T(CY[i]) * d[i];
+            tz += T(CZ[i]) * d[i];
+        } else if (ca == -n) {
+            s_known += d[i];
         }
     }
     s_tan += rb * T(2.0 / 3.0);
-    s_neg += rb * T(1.0 / 6.0);
-    s_pos += rb * T(1.0 / 6.0);
+    s_known += rb * T(1.0 / 6.0);
+    const T Fa = a == 0 ? Fx : (a == 1 ? Fy : Fz);
     T Jx, Jy, Jz;
-    if (is_in) {
+    if (velocity) {
         const T ux = T(P.bc_u[0]), uy = T(P.bc_u[1]), uz = T(P.bc_u[2]);
-        const T r = INC ? T(1) : (s_tan + T(2) * s_neg - T(0.5) * Fx) / (T(1) - ux);
-        Jx = r * ux - T(0.5) * Fx;
-        Jy = r * uy - T(0.5) * Fy;
-        Jz = r * uz - T(0.5) * Fz;
+        const T ua = a == 0 ? ux : (a == 1 ? uy : uz);
+        const T rho = INC ? T(1) : (s_tan + T(2) * s_known - T(0.5) * T(n) * Fa) / (T(1) - T(n) * ua);
+        Jx = rho * ux - T(0.5) * Fx;
+        Jy = rho * uy - T(0.5) * Fy;
+        Jz = rho * uz - T(0.5) * Fz;
     } else {
-        Jx = s_tan + T(2) * s_pos - T(P.bc_rho);
-        Jy = -T(0.5) * Fy;
-        Jz = -T(0.5) * Fz;
+        const T Ja = T(n) * (T(P.bc_rho) - s_tan - T(2) * s_known);
+        Jx = a == 0 ? Ja : -T(0.5) * Fx;
+        Jy = a == 1 ? Ja : -T(0.5) * Fy;
+        Jz = a == 2 ? Ja : -T(0.5) * Fz;
     }
-    const T Ny = T(0.5) * ty - Jy * T(1.0 / 3.0), Nz = T(0.5) * tz - Jz * T(1.0 / 3.0);
+    const T Nx = a == 0 ? T(0) : T(0.5) * tx - Jx * T(1.0 / 3.0);
+    const T Ny = a == 1 ? T(0) : T(0.5) * ty - Jy * T(1.0 / 3.0);
+    const T Nz = a == 2 ? T(0) : T(0.5) * tz - Jz * T(1.0 / 3.0);
+    // the unknowns' opposites (c_a = -n) are known and never rebuilt here
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if (CX[i] == 0) continue;
-        if ((CX[i] > 0 && is_in) || (CX[i] < 0 && is_out)) {
-            const T cJ = T(CX[i]) * Jx + T(CY[i]) * Jy + T(CZ[i]) * Jz;
-            d[i] = d[opposite(i)] + T(6.0 * weight(i)) * cJ - T(CY[i]) * Ny - T(CZ[i]) * Nz;
-        }
+    for (int i = 1; i < Q; ++i) {
+        if (axis_c(a, i) != n) continue;
+        const T cJ = T(CX[i]) * Jx + T(CY[i]) * Jy + T(CZ[i]) * Jz;
+        d[i] = d[opposite(i)] + T(6.0 * weight(i)) * cJ - T(CX[i]) * Nx - T(CY[i]) * Ny - T(CZ[i]) * Nz;
     }
 }
 
@@ -645,7 +659,7 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
         for (int i = 0; i < Q; ++i) d[i] = C::dec(raw[i], a.P.inv_scale);
         T Fx, Fy, Fz;
         load_force<T>(a.P, t, lane, Fx, Fy, Fz);
-        if (a.P.bc) open_boundary<T, (MODEL & 1)>(d, a.P, t, Fx, Fy, Fz);
+        if (a.P.bc) open_boundary<T, (MODEL & 1)>(d, a.P, t, lane, Fx, Fy, Fz);
         collide_model<T, MODEL>(d, T(a.P.rho_base), T(a.P.omega), T(a.P.kg), Fx, Fy, Fz);
     }
     if constexpr (ST == LBM_F16S) {

@@ -22,9 +22,9 @@ struct Phys {
     double inv_nfluid; // 1 / N_fluid (adjoint loss normalisation)
     int f16_stochastic;       // FP16 stores with stochastic rounding
     uint32_t launch_counter;  // step launches so far (seeds the rounding bits)
-    const uint64_t *bc;       // open boundaries: [n_tiles][2] inlet / outlet node masks, or null
-    double bc_u[3];           // inlet velocity
-    double bc_rho;            // outlet density
+    const uint64_t *bc;       // open boundaries: [n_tiles][9] node mask + 64 node codes, or null
+    double bc_u[3];           // velocity of the velocity nodes
+    double bc_rho;            // density of the pressure nodes
 };
 
 struct Launch {

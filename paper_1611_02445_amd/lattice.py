@@ -161,9 +161,12 @@ class Lattice:
             call("lbm_set_force", self.ctx, gx, gy, gz, None, None)
 
     def set_boundaries(self, types, u_in=(0.0, 0.0, 0.0), rho_out=1.0):
-        """Open boundaries on faces normal to x: types is a uint8 array over the
-        padded box [nz, ny, nx] (0 none, 1 velocity inlet u_in, 2 pressure
-        outlet rho_out), or None to remove them."""
+        """Open boundaries: types is a uint8 array over the padded box
+        [nz, ny, nx] of node codes (0 none; 1..12: axis (code-1)//4, and
+        (code-1)%4 = 0 velocity node rebuilding c_a = +1, 1 pressure node
+        rebuilding c_a = -1, 2 velocity c_a = -1, 3 pressure c_a = +1; 1 and 2
+        are the x inlet and outlet).  Velocity nodes get u_in, pressure nodes
+        rho_out.  None removes them."""
         if types is None:
             call("lbm_set_boundaries", self.ctx, None, 0.0, 0.0, 0.0, 1.0, None)
             return

@@ -82,7 +82,7 @@ def test_boundary_buffer_size():
     t = Tiling(np.zeros((8, 12, 16), np.uint8), 7)
     sz = _abi.Sizes()
     _abi.call("lbm_required_bytes", t._ptr, ctypes.byref(_params()), ctypes.byref(sz))
-    assert sz.bc_bytes == 24 * 2 * 8
+    assert sz.bc_bytes == 24 * 72
 
 
 def test_create_rejects_inconsistent_tiles():

@@ -58,6 +58,43 @@ def test_open_channel_matches_oracle(model):
     assert err <= 1e-12
 
 
+def _along(solid, bt, axis, u):
+    """The x channel turned so that it runs along `axis` (1 y, 2 z): arrays
+    transposed, codes 1/2 moved to that axis, velocity and periodic bits
+    permuted with it."""
+    if axis == 1:
+        sol, b = solid.transpose(0, 2, 1), bt.transpose(0, 2, 1)
+        u2, per = (u[1], u[0], u[2]), 4
+    else:
+        sol, b = solid.transpose(2, 1, 0), bt.transpose(2, 1, 0)
+        u2, per = (u[2], u[1], u[0]), 1
+    b = np.where(b > 0, b + 4 * axis, 0).astype(np.uint8)
+    return np.ascontiguousarray(sol), np.ascontiguousarray(b), u2, per
+
+
+@pytest.mark.parametrize("axis", [1, 2])
+@pytest.mark.parametrize("model,storage", [("qc", "f64"), ("mrt-inc", "f64"), ("qc", "f32")])
+def test_open_channel_along_other_axes(axis, model, storage):
+    solid, bt = _open_channel(32, 10, 8)
+    u = (0.02, 0.001, -0.002)
+    sol, b, u2, per = _along(solid, bt, axis, u)
+    log(f"[case] open channel along axis {axis} model={model} storage={storage}")
+    steps = 200
+    lat, sp, _, got, ref = _compare(sol, b, per, 0.8, steps, u2, 1.0, model=model, storage=storage)
+    if storage == "f64":
+        err = rel_err_f(got, ref, sp)
+        log(f"   f rel err {err:.3e}")
+        assert err <= 1e-12
+    else:
+        fl = sp == 0
+        _, w, _ = O.lattice()
+        d = np.abs(ref - w[:, None, None, None])[:, fl].max()
+        err = np.abs(got[:, fl] - ref[:, fl]).max()
+        bound = steps * 2.0 ** -24 * d * 8
+        log(f"   max |df| {err:.3e} bound {bound:.3e}")
+        assert err <= bound
+
+
 def test_porous_plug_with_force_and_perturbation():
     plug, _ = I.sphere_pack((8, 14, 24), 0.6, 1.5, 3.0, seed=17, periodic=False)
     plug[:, :, :4] = 0  # keep the inlet and outlet planes open
@@ -102,7 +139,7 @@ def test_boundaries_validated_and_removable():
     with pytest.raises(LbmError):
         lat.set_boundaries(bad, u_in=(0.01, 0, 0))
     with pytest.raises(LbmError):
-        lat.set_boundaries(bt * 3)
+        lat.set_boundaries(bt * 7)  # codes 7 and 14: 14 is not a code
     lat.set_boundaries(bt, u_in=(0.01, 0, 0))
     lat.set_boundaries(None)
     lat.init()
