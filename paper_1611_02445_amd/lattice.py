@@ -31,12 +31,16 @@ class Tiling:
         ptr = ctypes.POINTER(_abi.Tiles)()
         call("lbm_build_tiles", s.ctypes.data_as(ctypes.c_void_p), nx, ny, nz, int(periodic), ctypes.byref(ptr))
         self._ptr = ptr
+        self._free = _abi.lib().lbm_tiles_free
         self.shape_in = s.shape
 
     def __del__(self):
+        # at interpreter shutdown module globals may already be gone: the
+        # library handle is kept on the object
         p = getattr(self, "_ptr", None)
-        if p:
-            _abi.lib().lbm_tiles_free(p)
+        free = getattr(self, "_free", None)
+        if p and free is not None:
+            free(p)
             self._ptr = None
 
     @property
@@ -109,11 +113,13 @@ class Lattice:
         call("lbm_create", self.tiling._ptr, ctypes.byref(self.params), _vp(self.state_a), _vp(self.state_b),
              _vp(self.tables), _vp(self.scratch), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
         self.ctx = ctx
+        self._destroy = _abi.lib().lbm_destroy
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx:
-            _abi.lib().lbm_destroy(ctx)
+        destroy = getattr(self, "_destroy", None)
+        if ctx and destroy is not None:
+            destroy(ctx)
             self.ctx = None
 
     # -- sizes ---------------------------------------------------------------
