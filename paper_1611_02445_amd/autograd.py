@@ -1,8 +1,9 @@
 """Gradient of the mean fluid x-velocity after T steps, with checkpointing.
 
 Forward map (one fused step of the library): s_t = C(S s_{t-1}, F), with S the
-pull streaming with bounce-back and C the local LBGK + Guo collision.  The loss
-is L = (1/N_fluid) sum_fluid u_x(s_T).  The reverse sweep runs the library's
+pull streaming with bounce-back and C the local collision of the lattice's
+model (LBGK or LBMRT, either equilibrium) with Guo forcing.  The loss is
+L = (1/N_fluid) sum_fluid u_x(s_T).  The reverse sweep runs the library's
 adjoint kernels:
 
     seed(s_{T-1})                    -> eta_T,      grad_g  = ...
