@@ -22,7 +22,8 @@
  *     forcing is our reading: Guo, Zheng and Shi (2002) -- velocity shifted by
  *     F/2 and a second-order source term.
  *   - a discrete adjoint (reverse mode) of T steps for the loss
- *     "mean x-velocity over fluid nodes", storing every state,
+ *     "mean x-velocity over fluid nodes", storing every state, for every
+ *     collision model,
  *   - the multiple-relaxation-time operator the paper names for its LBMRT
  *     kernels (Section 2.2; no matrix given): the D3Q19 moment basis and
  *     relaxation rates of d'Humieres et al. (2002), both equilibria,

@@ -127,7 +127,7 @@ def plan_checkpoints(T, max_lattices, max_levels=3):
 
 class CheckpointedAdjoint:
     """Forward run with checkpoints and the matching reverse sweep on a Lattice
-    (FP64 or FP32 storage, quasi-compressible model).  Intervals: K for the
+    (FP64 or FP32 storage, any collision model).  Intervals: K for the
     forward checkpoints, then optional inner intervals K2 > K3 > ..."""
 
     def __init__(self, lat: Lattice, T: int, K: int, *inner):
