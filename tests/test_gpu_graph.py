@@ -57,3 +57,32 @@ def test_graph_refuses_stochastic_fp16_and_handles_empty():
     empty = new_lattice(np.ones((8, 8, 8), np.uint8), 0.8, 7)
     empty.init()
     empty.step(65, graphed=True)
+
+
+@pytest.mark.parametrize("model", ["mrt-qc", "inc"])
+def test_graph_with_open_boundaries_and_other_models(model):
+    """Boundary masks and the model are captured with the kernel arguments;
+    removing the boundaries triggers a recapture."""
+    import torch
+    solid = np.zeros((8, 12, 32), np.uint8)
+    solid[:, 0, :] = 1
+    solid[:, -1, :] = 1
+    bt = np.zeros_like(solid)
+    bt[:, 1:-1, 0] = 1
+    bt[:, 1:-1, -1] = 2
+    lats = []
+    for _ in range(2):
+        lat = new_lattice(solid, 0.8, 4, model=model)
+        lat.init()
+        lat.set_boundaries(bt, u_in=(0.02, 0.0, 0.0))
+        lats.append(lat)
+    plain, graphed = lats
+    for k, n in enumerate((40, 64, 3, 70)):
+        if k == 2:
+            for lat in lats:
+                lat.set_boundaries(None)
+        plain.step(n)
+        graphed.step(n, graphed=True)
+        torch.cuda.synchronize()
+        log(f"[case] graph {model} with boundaries call {k} n={n}")
+        assert torch.equal(plain.get_state(), graphed.get_state())
