@@ -234,3 +234,33 @@ def test_wide_offsets_adjoint_bitwise_identical(storage):
         res.append((L, gs.cpu().numpy(), gg.cpu().numpy()))
     assert res[0][0] == res[1][0]
     assert np.array_equal(res[0][1], res[1][1]) and np.array_equal(res[0][2], res[1][2])
+
+
+def _random_cases(n, seed):
+    """Seeded random small geometries: each axis 5..20 nodes, periodic axes
+    rounded to whole tiles, solid fraction 0.1..0.9 (down to tiles with a
+    single fluid node), every model, tau and force."""
+    rng = np.random.default_rng(seed)
+    models = ["qc", "inc", "mrt-qc", "mrt-inc"]
+    for k in range(n):
+        periodic = int(rng.integers(0, 8))
+        dims = []
+        for axis in range(3):  # x, y, z -> bits 1, 2, 4
+            d = int(rng.integers(5, 21))
+            if periodic >> axis & 1:
+                d = max(4, d // 4 * 4)
+            dims.append(d)
+        nx, ny, nz = dims
+        solid = I.random_bitmap((nz, ny, nx), float(rng.uniform(0.1, 0.9)), seed=int(rng.integers(1 << 30)))
+        yield (k, solid, periodic, float(rng.uniform(0.55, 1.4)), models[k % 4],
+               tuple(float(v) for v in rng.normal(0, 1e-5, 3)), int(rng.integers(1 << 30)))
+
+
+@pytest.mark.parametrize("case", list(_random_cases(16, 2024)), ids=lambda c: f"rand{c[0]}")
+def test_random_geometries(case):
+    """Random geometries exercise unusual tile masks (single fluid nodes,
+    checkerboards, empty neighbours) in every model; FP64 bar."""
+    k, solid, periodic, tau, model, g, seed = case
+    if (solid == 0).sum() == 0:
+        pytest.skip("no fluid node")
+    _run_case(f"random{k}", solid, periodic, tau, 25, g=g, model=model, seed=seed % 1000)
