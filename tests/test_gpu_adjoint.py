@@ -330,3 +330,46 @@ def test_adjoint_refuses_what_it_does_not_differentiate():
     lat.set_boundaries(types, u_in=(0.01, 0.0, 0.0))
     with pytest.raises(LbmError, match="UNSUPPORTED"):
         lat.adjoint_seed(lat.current_state(), lat.new_adjoint(), lat.new_grad())
+
+
+def _random_adjoint_cases(n, seed):
+    rng = np.random.default_rng(seed)
+    models = ["qc", "inc", "mrt-qc", "mrt-inc"]
+    for k in range(n):
+        periodic = int(rng.integers(0, 8))
+        dims = []
+        for axis in range(3):
+            d = int(rng.integers(5, 17))
+            if periodic >> axis & 1:
+                d = max(4, d // 4 * 4)
+            dims.append(d)
+        nx, ny, nz = dims
+        solid = I.random_bitmap((nz, ny, nx), float(rng.uniform(0.1, 0.7)), seed=int(rng.integers(1 << 30)))
+        yield (k, solid, periodic, float(rng.uniform(0.6, 1.2)), models[k % 4], int(rng.integers(2, 8)),
+               int(rng.integers(1 << 30)))
+
+
+@pytest.mark.parametrize("case", list(_random_adjoint_cases(8, 77)), ids=lambda c: f"rand{c[0]}")
+def test_adjoint_random_geometries(case):
+    import torch
+    from paper_1611_02445_amd.autograd import CheckpointedAdjoint
+    k, s, periodic, tau, model, K, seed = case
+    if (s == 0).sum() == 0:
+        pytest.skip("no fluid node")
+    T = 9
+    sp = padded(s, periodic)
+    f0 = perturbed_state(sp, seed % 1000)
+    g = _force_field(sp, seed % 997)
+    log(f"[case] adjoint random{k} shape={s.shape} periodic={periodic} tau={tau:.2f} model={model} K={K}")
+    Lo, gs_o, gF_o = O.adjoint(f0, sp, tau, g, T, periodic=periodic, model=O.MODELS[model])
+    lat = new_lattice(s, tau, periodic, model=model)
+    lat.set_force(torch.from_numpy(g).cuda())
+    run = CheckpointedAdjoint(lat, T, K)
+    run.forward(torch.from_numpy(f0))
+    gs, gg = run.backward()
+    gs, gg = gs.cpu().numpy(), gg.cpu().numpy()
+    fl = sp == 0
+    es = np.max(np.abs(gs[:, fl] - gs_o[:, fl])) / np.abs(gs_o[:, fl]).max()
+    eg = np.max(np.abs(gg[:, fl] - gF_o[:, fl])) / np.abs(gF_o[:, fl]).max()
+    log(f"   dL/ds0 err {es:.2e}  dL/dg err {eg:.2e}")
+    assert es <= 1e-11 and eg <= 1e-11
