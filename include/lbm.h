@@ -23,7 +23,11 @@
  *   - tile-order buffers are [n_tiles][components][64], tiles in the
  *     context's device order (see tile_order); lbm_tiles_to_dense converts;
  *   - device pointers are plain HIP device addresses owned by the caller; the
- *     library never allocates device memory;
+ *     library allocates no device buffers (lbm_step_graphed alone creates a
+ *     private stream and executable graphs, held by the context until
+ *     lbm_destroy);
+ *   - a context is not thread-safe: one host thread at a time may call into
+ *     it; distinct contexts are independent;
  *   - every call returns an lbm_status; on failure lbm_last_error() gives a
  *     thread-local message.  Nothing crosses the ABI as a C++ exception.
  *   - kernel launches are asynchronous on the context's stream; errors of a
