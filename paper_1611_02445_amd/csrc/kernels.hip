@@ -1235,8 +1235,20 @@ __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
 
 // step: lam_{t-1} = S^T eta_t (reverse gather), g_{t-1} = S s_{t-2},
 // eta_{t-1} = J^T lam_{t-1}, grad += rho0 (dC/dF)^T lam_{t-1}
+// Waves per SIMD the adjoint step asks the register allocator for.  The
+// FP32 quasi-compressible LBMRT step with 32-bit offsets needs 131 VGPRs
+// unconstrained (3 waves); at 4 it fits 128 with no spill and runs 6%
+// faster.  Every other instance keeps the allocator's choice: at 4 waves the
+// 64-bit-offset one spills, and the FP64 ones spill and cost 33% (LBGK) to
+// 3.4x (LBMRT).
 template <int ST, int MODEL, typename OffT>
-__global__ __launch_bounds__(512) void k_adj_step(AdjArgs a) {
+struct AdjWaves {
+    static constexpr int value = (ST == 1 && MODEL == 2 && sizeof(OffT) == 4) ? 4 : 1;
+};
+
+template <int ST, int MODEL, typename OffT>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(AdjWaves<ST, MODEL, OffT>::value))) void k_adj_step(
+    AdjArgs a) {
     using T = typename Codec<ST>::S;
     const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
