@@ -289,12 +289,13 @@ def test_adjoint_f32_against_f64_sphere_pack():
     assert eL <= 1e-3
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_adjoint_independent_of_launch_configuration(storage):
+@pytest.mark.parametrize("storage,model", [("f64", "qc"), ("f32", "qc"), ("f64", "mrt-qc")])
+def test_adjoint_independent_of_launch_configuration(storage, model):
     """Tile order, tiles per workgroup and 64-bit offsets change where tiles
     live and when they run, not what an adjoint step computes per node: the
     gradients are bitwise equal (the loss, an FP64 sum in tile order, to the
-    last bits)."""
+    last bits).  The library's own choice (one tile per workgroup for the
+    FP64 LBMRT adjoint, four otherwise) is one of the configurations."""
     import torch
     from paper_1611_02445_amd.autograd import CheckpointedAdjoint
     tau, T = 0.75, 17
@@ -303,14 +304,14 @@ def test_adjoint_independent_of_launch_configuration(storage):
     f0 = torch.from_numpy(perturbed_state(sp, 12))
     g = torch.from_numpy(_force_field(sp, 13)).cuda()
     out = []
-    for kw in (dict(tile_order=1), dict(tile_order=2), dict(tile_order=3), dict(tile_order=4, tiles_per_wg=1),
-               dict(tiles_per_wg=8), dict(wide_offsets=True)):
-        lat = new_lattice(s, tau, 7, storage=storage, **kw)
+    for kw in (dict(), dict(tiles_per_wg=4), dict(tile_order=1), dict(tile_order=2), dict(tile_order=3),
+               dict(tile_order=4, tiles_per_wg=1), dict(tiles_per_wg=8), dict(wide_offsets=True)):
+        lat = new_lattice(s, tau, 7, storage=storage, model=model, **kw)
         lat.set_force(g)
         run = CheckpointedAdjoint(lat, T, 6)
         L = run.forward(f0)
         gs, gg = run.backward()
-        log(f"[case] adjoint {storage} {kw}: L {L:.15e}")
+        log(f"[case] adjoint {storage} {model} {kw}: L {L:.15e}")
         out.append((L, gs.cpu().numpy(), gg.cpu().numpy()))
     for L, gs, gg in out[1:]:
         assert abs(L - out[0][0]) <= 1e-14 * abs(out[0][0])
