@@ -64,6 +64,7 @@ def lib():
         L.oracle_adjoint.restype = f64
         L.oracle_mrt_matrix.argtypes = [P, P]
         L.oracle_mrt_rates.argtypes = [f64, P]
+        L.oracle_set_mrt_ghost_rates.argtypes = [P]
         L.oracle_collide_mrt_rates.argtypes = [i32, P, P, P, P]
         L.oracle_zou_he.argtypes = [i32, i32, P, f64, P, P]
         L.oracle_run_bc.argtypes = [P, P, P, i32, i32, i32, i32, i32, f64, P, f64, f64, f64, i32, P, P, f64]
@@ -122,6 +123,23 @@ def mrt_rates(tau):
     s = np.zeros(Q)
     lib().oracle_mrt_rates(float(tau), _p(s))
     return s
+
+
+class mrt_ghost_rates:
+    """Context manager: run the multiple-relaxation-time operator with the
+    rates (s_e, s_eps, s_q, s_pi, s_m) instead of the table's, restoring the
+    table on exit."""
+
+    def __init__(self, s_e=1.19, s_eps=1.4, s_q=1.2, s_pi=1.4, s_m=1.98):
+        self.r = np.array([s_e, s_eps, s_q, s_pi, s_m], dtype=np.float64)
+
+    def __enter__(self):
+        lib().oracle_set_mrt_ghost_rates(_p(self.r))
+        return self
+
+    def __exit__(self, *exc):
+        lib().oracle_set_mrt_ghost_rates(None)
+        return False
 
 
 def collide_mrt_rates(fin, F, s, model=2):

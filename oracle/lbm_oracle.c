@@ -31,11 +31,13 @@
  *     names for its open boundaries (Section 2.2), on faces normal to any
  *     axis.
  *
- * Parity unpinned: the rates of the moments eps, q, pi and m (1.4, 1.2,
- * 1.4, 1.98).  They act below the Navier-Stokes level, so no transport
+ * Parity unpinned: the rates of the moments eps and pi (1.4, 1.4).  They
+ * act below the Navier-Stokes level on moments that are even in every
+ * velocity component a plane or sound-wave test excites, so no transport
  * coefficient or closed form fixes them; they are the cited paper's values.
- * The shear rate (1/tau) and the energy rate (1.19, through the bulk
- * viscosity) are pinned.
+ * The shear rate (1/tau), the energy rate (1.19, through the bulk
+ * viscosity) and the q and m rates (1.2, 1.98, through the wall slip of
+ * halfway bounce-back in plane Poiseuille flow) are pinned.
  *
  * Arithmetic is plain C in double precision with the operations written in
  * the order of the formulas; build without FMA contraction.
@@ -173,10 +175,22 @@ static double mrt_row(int k, int i) {
 /* relaxation rates of the same paper; the viscous moments relax at 1/tau
  * (so nu = (tau - 1/2)/3 as for the single-time operator); the rates of the
  * conserved moments (rho, j) do not enter */
+static const double GHOST_DEFAULT[5] = {1.19, 1.4, 1.2, 1.4, 1.98};
+static double GHOST[5] = {1.19, 1.4, 1.2, 1.4, 1.98}; /* e, eps, q, pi, m */
 static void mrt_rates(double tau, double s[Q]) {
     const double sv = 1.0 / tau;
-    const double r[Q] = {0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, sv, 1.4, sv, 1.4, sv, sv, sv, 1.98, 1.98, 1.98};
+    const double e = GHOST[0], ep = GHOST[1], q = GHOST[2], pi = GHOST[3], m = GHOST[4];
+    const double r[Q] = {0.0, e, ep, 0.0, q, 0.0, q, 0.0, q, sv, pi, sv, pi, sv, sv, sv, m, m, m};
     for (int k = 0; k < Q; ++k) s[k] = r[k];
+}
+
+/* Test hook: the rates of the e, eps, q, pi and m moments used by every
+ * later step and adjoint of the multiple-relaxation-time operator (NULL
+ * restores the table above).  Lets the tests check closed forms that depend
+ * on these rates at more than one value; not thread-safe against a running
+ * step. */
+void oracle_set_mrt_ghost_rates(const double *r /*[5] or NULL*/) {
+    for (int k = 0; k < 5; ++k) GHOST[k] = r ? r[k] : GHOST_DEFAULT[k];
 }
 
 /* M (rows k, columns i) and its inverse by Gauss-Jordan elimination, built

@@ -149,14 +149,20 @@ def test_boundaries_validated_and_removable():
     assert (lat.get_state() - f0).abs().max().item() <= 1e-15
 
 
-@pytest.mark.parametrize("model", ["qc", "inc"])
+_LBMRT_LID = ("the Zou-He velocity node with the LBMRT m rate 1.98 is linearly unstable at tau 0.6: a perturbation "
+              "grows ~2600-fold in 200 steps in the oracle (tests/test_oracle_bc.py::"
+              "test_velocity_layer_unstable_with_the_lbmrt_m_rate_at_small_tau), so both sides diverge and there is "
+              "no result to compare")
+
+
+@pytest.mark.parametrize("model", ["qc", "inc", pytest.param("mrt-qc", marks=pytest.mark.skip(reason=_LBMRT_LID))])
 def test_lid_driven_cavity(model):
     """The paper's cavity3D: a closed box with bounce-back walls whose top
     fluid layer is a velocity node moving at U along x (code 11: axis z,
     rebuilding the populations with c_z = -1).  LBGK only: with the LBMRT
-    rates this lid, where it meets the walls, drives a growing mode in the
-    oracle and the kernel alike (a property of the discrete scheme; the same
-    operator is stable in Couette flow under the same lid)."""
+    rates at tau = 0.6 the velocity layer has a linearly unstable mode, in the
+    oracle and the kernel alike (a property of the discrete scheme, shown on
+    the CPU by the oracle test named in the skip reason)."""
     n = 16
     solid = np.zeros((n, n, n), np.uint8)
     bt = np.zeros_like(solid)

@@ -159,3 +159,41 @@ def test_couette_quasi_compressible_lbmrt_deviates_at_third_order():
     ratio = np.abs(d1).max() / np.abs(d2).max()
     assert 7.0 <= ratio <= 9.0
     assert np.abs(d1).max() <= 1e-6
+
+
+def _lid_amplification(model, s_m, tau, noise, steps=200, n=8):
+    """Growth of a small random perturbation of the rest state over `steps`
+    steps under a velocity layer at rest (code 11, u = 0) above a wall,
+    periodic in x and y: max |f - f_rest| after over before."""
+    solid = np.zeros((n, n, n), np.uint8)
+    solid[0] = 1
+    bt = np.zeros_like(solid)
+    bt[-1] = 11
+    rest = O.init(solid, model=model)
+    rng = np.random.default_rng(1)
+    f = rest * (1.0 + noise * rng.uniform(-1, 1, rest.shape))
+    f[:, solid == 1] = 0.0
+    d0 = np.abs(f - rest).max()
+    with O.mrt_ghost_rates(s_m=s_m):
+        f = O.run_bc(f, solid, tau, steps, bt, u_in=(0.0, 0.0, 0.0), periodic=3, model=model)
+    return np.abs(f - rest).max() / d0
+
+
+def test_velocity_layer_unstable_with_the_lbmrt_m_rate_at_small_tau():
+    """The Zou-He velocity node combined with the multiple-relaxation-time
+    operator has a linearly unstable mode when the rate of the third-order m
+    moments is close to 2 and tau is small: at tau = 0.6 with the table's
+    s_m = 1.98 a perturbation of the rest state grows ~2600-fold in 200 steps,
+    by the same factor for perturbations 1000 times apart (a linear mode, not
+    a nonlinear effect of the lid speed), for both equilibria.  The same layer
+    damps it with s_m = 1.8, at tau = 0.8, or with the single-relaxation-time
+    operator.  This is why the LBMRT rows of the dense lid-driven cavity study
+    run the walled box without a lid: a lid at tau = 0.6 diverges in the oracle
+    and in the kernel alike, whatever its speed."""
+    a = _lid_amplification(2, 1.98, 0.6, 1e-12)
+    b = _lid_amplification(2, 1.98, 0.6, 1e-9)
+    assert a >= 100.0 and abs(a / b - 1.0) <= 0.01
+    assert _lid_amplification(3, 1.98, 0.6, 1e-12) >= 100.0
+    assert _lid_amplification(2, 1.8, 0.6, 1e-12) <= 0.1
+    assert _lid_amplification(2, 1.98, 0.8, 1e-12) <= 0.1
+    assert _lid_amplification(0, 1.98, 0.6, 1e-12) <= 0.1

@@ -10,12 +10,14 @@ space).  What fixes it independently of the code:
     the weights (sums of w_i c_i^n over the velocity set);
   - mass is conserved, momentum grows by exactly F, a rest state stays;
   - a steady plane channel has the curvature -g/nu of the Navier-Stokes
-    solution, nu = (tau - 1/2)/3, in the bulk;
+    solution, nu = (tau - 1/2)/3, in the bulk, and the wall slip of halfway
+    bounce-back that the q and m rates set (a closed form derived below);
   - each rate moves only its own moment, by the factor 1 - s_k;
   - a standing sound wave decays at the longitudinal viscosity that the
     energy rate sets through the bulk viscosity.
-The rates of the eps, q, pi and m moments act below the Navier-Stokes level:
-no pin here fixes their values (parity unpinned beyond the kernel)."""
+The q and m rates are pinned through the wall slip.  The rates of the eps and
+pi moments act below the Navier-Stokes level and enter no closed form here:
+their values are parity unpinned beyond the kernel."""
 import numpy as np
 import pytest
 
@@ -102,6 +104,51 @@ def test_plane_channel_curvature(tau, model):
     d2 = ux[:, 2:, :] - 2 * ux[:, 1:-1, :] + ux[:, :-2, :]
     assert np.abs(d2 / (-g / nu) - 1.0).max() <= 1e-8
     assert np.abs(u[1]).max() <= 1e-14 and np.abs(u[2]).max() <= 1e-14
+
+
+def _steady_plane_channel(tau, model, H, g):
+    nu = (tau - 0.5) / 3.0
+    solid = I.plane_channel(4, H, 4)
+    steps = int(12 * H * H / nu)
+    f = O.run(O.init(solid, model=model), solid, tau, steps, force=[g, 0, 0], periodic=7, model=model)
+    _, u = O.macroscopic(f, solid, force=[g, 0, 0], model=model)
+    return u[0][0, 1:-1, 0]
+
+
+@pytest.mark.parametrize("tau,model,H,s_q,s_m", [
+    (0.6, 2, 10, 1.2, 1.98), (0.8, 2, 10, 1.2, 1.98), (1.1, 3, 12, 1.2, 1.98),  # the table's rates
+    (0.8, 2, 10, 1.6, 1.1), (0.7, 3, 8, 1.0, 1.5)])                              # other (s_q, s_m) pairs
+def test_plane_channel_wall_slip(tau, model, H, s_q, s_m):
+    """Steady plane Poiseuille flow between halfway bounce-back walls is exactly
+    parabolic with a uniform slip that the odd ghost rates set:
+        u(y) = g/(2 nu) (H^2/4 - r^2) + g (1/(2 s_q) + 3/(2 s_m) - 1 - 1/(8 nu)),
+    r the distance from the mid-plane, H the number of fluid rows.
+    Derivation (linear in u; the flow varies along y only): the x-odd, z-even
+    part of a node's populations spans four moments, j_x, q_x (rate s_q),
+    p_xy (rate 1/tau) and m_x (rate s_m).  Away from the walls q_x + 2 j_x/3 and
+    m_x settle at the constants -(5/3) F (1 - s_q)/s_q and -F (1 - s_m)/s_m
+    after each collision, while the part that streams along y,
+    sigma = j/3 + (q_x + 2 j/3)/10 + m_x/2, is a parabola of curvature set by
+    1/tau alone.  Halfway bounce-back is met exactly by that parabola and
+    p_xy, so u = (j - F/2)/rho0 inherits the two constants through
+    j = 3 sigma - 3 (q_x + 2 j/3)/10 - 3 m_x/2.  With every rate equal to
+    1/tau this is the single-relaxation-time slip g (6 nu - 1/(8 nu)), and with
+    s_q = s_m the magic-parameter form (g/(2 nu))(16 Lambda - 3)/12,
+    Lambda = (1/s_nu - 1/2)(1/s_odd - 1/2).  The weights 1 : 3 pin which rate
+    belongs to q_x and which to m_x; the eps and pi rates (x-even moments) do
+    not enter.  g = 1e-7 keeps the O(u^2) terms of the equilibrium below the
+    tolerance."""
+    g = 1e-7
+    nu = (tau - 0.5) / 3.0
+    with O.mrt_ghost_rates(s_q=s_q, s_m=s_m):
+        ux = _steady_plane_channel(tau, model, H, g)
+    r = np.arange(1, H + 1) - (H + 1) / 2.0
+    slip = g * (1.0 / (2.0 * s_q) + 3.0 / (2.0 * s_m) - 1.0 - 1.0 / (8.0 * nu))
+    expect = g / (2.0 * nu) * (H * H / 4.0 - r * r) + slip
+    assert np.abs(ux - expect).max() <= 1e-8 * np.abs(expect).max()
+    # the single-relaxation-time slip is not what this operator gives
+    bgk = g / (2.0 * nu) * (H * H / 4.0 - r * r) + g * (6.0 * nu - 1.0 / (8.0 * nu))
+    assert np.abs(ux - bgk).max() >= 1e-5 * np.abs(expect).max()
 
 
 def test_viscous_rates():
