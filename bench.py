@@ -62,8 +62,10 @@ def build_case(args):
 def time_storage(solid, storage, args, torch, want_state=False, model="qc"):
     from paper_1611_02445_amd.lattice import Lattice
     # "f32u": FP32 storage of f itself (the paper's form), an ablation of the shift
+    # check_u_max: every macroscopic call of the run fails if the compressibility
+    # limit u_max <= 0.05 (Section 2.2) is exceeded
     lat = Lattice(solid, args.tau, periodic=7, storage="f32" if storage == "f32u" else storage, model=model,
-                  tiles_per_wg=args.tpw, tile_order=args.order, f32_unshifted=storage == "f32u")
+                  tiles_per_wg=args.tpw, tile_order=args.order, f32_unshifted=storage == "f32u", check_u_max=True)
     lat.init()
     lat.set_force((args.g, 0.0, 0.0))
     log(f"[bench] {storage}: tiles={lat.n_tiles} fluid={lat.n_fluid} eta_t={lat.tiling.eta_t:.4f}")
@@ -656,6 +658,7 @@ def main():
         "permeability": r["k"],
         "steps_total": r["steps_done"],
         "mass": r["sums"][0],
+        "u_max": r["sums"][5],
     }
     if traffic is not None:
         result["roofline"]["traffic_bytes_per_fluid_update"] = round(traffic / nf, 1)

@@ -52,7 +52,8 @@ typedef enum {
     LBM_E_HIP = -4,         /* a HIP runtime call or launch failed */
     LBM_E_STATE = -5,       /* call not valid in the context's current state */
     LBM_E_UNSUPPORTED = -6, /* option combination not built */
-    LBM_E_NUMERIC = -7      /* non-finite values found by a checking call */
+    LBM_E_NUMERIC = -7      /* a checking call found non-finite values, or a fluid speed above the
+                               compressibility limit when that check is on (check_u_max) */
 } lbm_status;
 
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2 } lbm_storage;
@@ -132,7 +133,16 @@ typedef struct lbm_params {
     int32_t f32_unshifted;  /* LBM_F32 only: 1 stores f_i itself instead of f_i - w_i rho0 (the
                                paper's FP32 storage; kept as an ablation of the shift), 0 =
                                shifted (default).  Must be 0 for other storage types. */
+    int32_t check_u_max;    /* 1 = lbm_macroscopic, lbm_macroscopic_buf and lbm_permeability
+                               return LBM_E_NUMERIC (after filling their outputs)
+                               when the largest fluid speed max |u| exceeds LBM_U_MAX = 0.05, the
+                               bound on the macroscopic velocity that keeps the compressibility
+                               error of the quasi-compressible model small (Section 2.2);
+                               0 = no check (default). */
 } lbm_params;
+
+/* The compressibility limit checked when lbm_params.check_u_max is set. */
+#define LBM_U_MAX 0.05
 
 typedef struct lbm_sizes {
     size_t state_bytes;      /* one lattice: per tile 19*k values (k fluid nodes) padded to whole
@@ -161,7 +171,8 @@ int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *params, lbm_siz
  * returning, so `tiles` may be freed afterwards.  Parameters are validated
  * (LBM_E_INVAL): tau > 1/2, rho0 > 0, known storage and model, f16 scale in
  * [0,30], tiles_per_wg in {0,1,2,4,8}, f16_rounding in {0,1}, tile_order in
- * 0..4, wide_offsets in {0,1}, f32_unshifted in {0,1} (1 only with LBM_F32);
+ * 0..4, wide_offsets in {0,1}, f32_unshifted in {0,1} (1 only with LBM_F32),
+ * check_u_max in {0,1};
  * the tables are checked (every neighbour index
  * in [-1, n_tiles), each tile its own centre neighbour, no empty kept tile). */
 int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void *state_a, void *state_b,
@@ -234,8 +245,9 @@ int lbm_current_state(lbm_ctx *ctx, void **state);
  *            non-finite rho or u, and sum u_x (the adjoint's loss is
  *            sums[7] / sums[4], the mean x-velocity over fluid nodes).
  *            Reduced in FP64 in a fixed order (bitwise reproducible).
- * Synchronises the stream.  Returns LBM_E_NUMERIC (after filling sums) when a
- * non-finite value was found. */
+ * Synchronises the stream.  Returns LBM_E_NUMERIC (after filling sums and the
+ * fields) when a non-finite value was found, or, with check_u_max set, when
+ * sums[5] = max |u| exceeds LBM_U_MAX. */
 int lbm_macroscopic(lbm_ctx *ctx, double *rho_dev, double *u_dev, double sums[8]);
 /* The same for any lattice buffer of the context. */
 int lbm_macroscopic_buf(lbm_ctx *ctx, const void *state, double *rho_dev, double *u_dev, double sums[8]);

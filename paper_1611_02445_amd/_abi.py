@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(PKG, "libtiledlbm.so")
 LBM_OK = 0
 STATUS = {0: "LBM_OK", -1: "LBM_E_INVAL", -2: "LBM_E_NOMEM", -3: "LBM_E_RANGE", -4: "LBM_E_HIP",
           -5: "LBM_E_STATE", -6: "LBM_E_UNSUPPORTED", -7: "LBM_E_NUMERIC"}
+STATUS_CODE = {name: code for code, name in STATUS.items()}
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2}
 MODEL = {"qc": 0, "quasi-compressible": 0, "inc": 1, "incompressible": 1, "mrt-qc": 2, "mrt-inc": 3}
 
@@ -44,7 +45,8 @@ class Params(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("rho0", ctypes.c_double), ("storage", ctypes.c_int32),
                 ("model", ctypes.c_int32), ("f16_log2_scale", ctypes.c_int32), ("tiles_per_wg", ctypes.c_int32),
                 ("f16_rounding", ctypes.c_int32), ("tile_order", ctypes.c_int32),
-                ("wide_offsets", ctypes.c_int32), ("f32_unshifted", ctypes.c_int32)]
+                ("wide_offsets", ctypes.c_int32), ("f32_unshifted", ctypes.c_int32),
+                ("check_u_max", ctypes.c_int32)]
 
 
 class Sizes(ctypes.Structure):

@@ -89,6 +89,8 @@ int check_params(const lbm_params *p) {
         return fail(LBM_E_INVAL, "f32_unshifted applies to FP32 storage only");
     if (p->f16_rounding != 0 && p->f16_rounding != 1)
         return fail(LBM_E_INVAL, "f16_rounding must be 0 (stochastic) or 1 (nearest) (got %d)", p->f16_rounding);
+    if (p->check_u_max != 0 && p->check_u_max != 1)
+        return fail(LBM_E_INVAL, "check_u_max must be 0 or 1 (got %d)", p->check_u_max);
     return LBM_OK;
 }
 
@@ -495,6 +497,16 @@ extern "C" int lbm_current_state(lbm_ctx *c, void **state) {
     return LBM_OK;
 }
 
+// the checks a synchronising macroscopic call applies to its reduced sums:
+// non-finite values always, the compressibility limit u_max <= 0.05
+// (Section 2.2) when the context asks for it
+static int check_sums(const lbm_ctx *c, const double *sums, const char *what) {
+    if (sums[6] > 0.0) return fail(LBM_E_NUMERIC, "%s: %.0f fluid nodes with non-finite values", what, sums[6]);
+    if (c->params.check_u_max && sums[5] > LBM_U_MAX)
+        return fail(LBM_E_NUMERIC, "%s: max |u| = %.6g exceeds the compressibility limit %g", what, sums[5], LBM_U_MAX);
+    return LBM_OK;
+}
+
 extern "C" int lbm_macroscopic_buf(lbm_ctx *c, const void *state, double *rho_dev, double *u_dev, double sums[8]) {
     CHECK_CTX(c);
     if (!sums) return fail(LBM_E_INVAL, "lbm_macroscopic: NULL sums");
@@ -514,8 +526,7 @@ extern "C" int lbm_macroscopic_buf(lbm_ctx *c, const void *state, double *rho_de
     if (e == hipSuccess) e = hipMemcpyAsync(sums, final_, NSUM * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "lbm_macroscopic");
-    if (sums[6] > 0.0) return fail(LBM_E_NUMERIC, "lbm_macroscopic: %.0f fluid nodes with non-finite values", sums[6]);
-    return LBM_OK;
+    return check_sums(c, sums, "lbm_macroscopic");
 }
 
 extern "C" int lbm_macroscopic(lbm_ctx *c, double *rho_dev, double *u_dev, double sums[8]) {

@@ -80,7 +80,7 @@ class Lattice:
 
     def __init__(self, solid, tau, periodic=0, rho0=1.0, storage="f64", model="qc", f16_log2_scale=20,
                  tiles_per_wg=0, device="cuda", tiling=None, stream=None, f16_rounding="stochastic",
-                 tile_order=0, wide_offsets=False, f32_unshifted=False):
+                 tile_order=0, wide_offsets=False, f32_unshifted=False, check_u_max=False):
         import torch
 
         self.torch = torch
@@ -91,7 +91,8 @@ class Lattice:
                                   tiles_per_wg=int(tiles_per_wg),
                                   f16_rounding={"stochastic": 0, "nearest": 1}[f16_rounding],
                                   tile_order=int(tile_order), wide_offsets=int(bool(wide_offsets)),
-                                  f32_unshifted=int(bool(f32_unshifted)))
+                                  f32_unshifted=int(bool(f32_unshifted)),
+                                  check_u_max=int(bool(check_u_max)))
         self.storage = storage
         self.tau = float(tau)
         self.rho0 = float(rho0)

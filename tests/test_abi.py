@@ -46,7 +46,8 @@ def _params(**kw):
 @pytest.mark.parametrize("bad", [dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(rho0=0.0),
                                  dict(storage=3), dict(model=4), dict(f16_log2_scale=31), dict(tiles_per_wg=3),
                                  dict(f16_rounding=2), dict(tile_order=5), dict(wide_offsets=2),
-                                 dict(f32_unshifted=2), dict(f32_unshifted=1, storage=0)])
+                                 dict(f32_unshifted=2), dict(f32_unshifted=1, storage=0),
+                                 dict(check_u_max=2), dict(check_u_max=-1)])
 def test_parameter_validation(bad):
     t = Tiling(np.zeros((8, 8, 8), np.uint8), 7)
     sz = _abi.Sizes()
@@ -99,3 +100,15 @@ def test_create_rejects_inconsistent_tiles():
         rc = _abi.lib().lbm_create(t._ptr, ctypes.byref(_params()), *dummy, None, ctypes.byref(ctx))
         assert rc == -1 and not ctx.value
         assert field.encode() in _abi.lib().lbm_last_error() or b"neighbour" in _abi.lib().lbm_last_error()
+
+
+def test_compressibility_limit_is_the_papers():
+    """The u_max check compares against 0.05 (Section 2.2), exported as
+    LBM_U_MAX, and is off unless asked for."""
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+LBM_U_MAX\s+([0-9.eE+-]+)", text)
+    assert m and float(m.group(1)) == 0.05
+    assert _abi.Params().check_u_max == 0
+    t = Tiling(np.zeros((8, 8, 8), np.uint8), 7)
+    sz = _abi.Sizes()
+    assert _abi.lib().lbm_required_bytes(t._ptr, ctypes.byref(_params(check_u_max=1)), ctypes.byref(sz)) == 0
