@@ -36,3 +36,15 @@ def rel_err_f(gpu, ora, solid_p):
 def new_lattice(solid, tau, periodic, **kw):
     from paper_1611_02445_amd.lattice import Lattice
     return Lattice(solid, tau, periodic=periodic, **kw)
+
+
+def elementwise_err(got, ref, mask, floor):
+    """Largest |got - ref| / max(|ref|, floor * max|ref|) over the entries of
+    the masked nodes (mask over the last three axes): a relative bound on
+    every entry, with an absolute floor for entries near zero."""
+    g = got[..., mask]
+    r = ref[..., mask]
+    if r.size == 0:
+        return 0.0
+    den = np.maximum(np.abs(r), floor * np.abs(r).max())
+    return float(np.max(np.abs(g - r) / den))

@@ -8,7 +8,11 @@ import pytest
 import oracle as O
 from paper_1611_02445_amd import inputs as I
 
-from helpers import log, new_lattice, padded, perturbed_state
+from helpers import elementwise_err, log, new_lattice, padded, perturbed_state
+
+# FP64 adjoint against the oracle's: every entry within 1e-11 relative, an
+# entry smaller than 1e-6 of the largest one measured against that floor
+F64_TOL, F64_FLOOR = 1e-11, 1e-6
 
 pytestmark = pytest.mark.gpu
 
@@ -48,10 +52,10 @@ def test_adjoint_matches_oracle(periodic, K, model):
     scale = (np.tensordot(np.abs(c[:, 0]).astype(float), fT, axes=1)[fl] / fT.sum(0)[fl]).mean()
     log(f"   L {L:.12e} vs {Lo:.12e} (bound {1e-12 * scale:.1e})")
     assert abs(L - Lo) <= 1e-12 * scale
-    es = np.max(np.abs(gs[:, fl] - gs_o[:, fl])) / np.abs(gs_o[:, fl]).max()
-    eg = np.max(np.abs(gg[:, fl] - gF_o[:, fl])) / np.abs(gF_o[:, fl]).max()
-    log(f"   dL/ds0 err {es:.2e}  dL/dg err {eg:.2e}")
-    assert es <= 1e-11 and eg <= 1e-11
+    es = elementwise_err(gs, gs_o, fl, F64_FLOOR)
+    eg = elementwise_err(gg, gF_o, fl, F64_FLOOR)
+    log(f"   per-entry dL/ds0 err {es:.2e}  dL/dg err {eg:.2e}")
+    assert es <= F64_TOL and eg <= F64_TOL
     assert np.all(gs[:, ~fl] == 0) and np.all(gg[:, ~fl] == 0)
     assert run.recompute_steps == T - run.n_ckpt
 
@@ -96,16 +100,16 @@ def test_autograd_function():
     (3.0 * L).backward()
     fl = sp == 0
     assert abs(L.item() - Lo) <= 1e-12 * abs(Lo)
-    assert np.max(np.abs(f0_t.grad.cpu().numpy()[:, fl] - 3 * gs_o[:, fl])) <= 1e-11 * 3 * np.abs(gs_o).max()
-    assert np.max(np.abs(g_t.grad.cpu().numpy()[:, fl] - 3 * gF_o[:, fl])) <= 1e-11 * 3 * np.abs(gF_o).max()
+    assert elementwise_err(f0_t.grad.cpu().numpy(), 3 * gs_o, fl, F64_FLOOR) <= F64_TOL
+    assert elementwise_err(g_t.grad.cpu().numpy(), 3 * gF_o, fl, F64_FLOOR) <= F64_TOL
 
 
 @pytest.mark.parametrize("model", ["qc", "mrt-qc"])
 def test_adjoint_full_size_finite_differences(model):
     """128^3 periodic sphere pack, porosity 0.5, radius U[4,12), tau 0.8,
     T = 2000, checkpoints every 100 steps, per-node g_x ~ N(1e-6, 1e-7).
-    Central differences of the GPU forward: g_x at 32 random fluid nodes,
-    f_i(0) for three directions at 4 of them."""
+    Central differences of the GPU forward: g_x at 32 random fluid nodes and
+    f_i(0) at the same 32 nodes, direction i cycling through all 19."""
     import torch
     from paper_1611_02445_amd.autograd import CheckpointedAdjoint
     tau, T, K = 0.8, 2000, 100
@@ -158,22 +162,27 @@ def test_adjoint_full_size_finite_differences(model):
         f.view(19, -1)[i, n] += e
         return loss(f, g_t)
 
-    for n in nodes[:4]:
-        for i in (0, 1, 11):
-            # The f0 gradients are ~1e-11..1e-10, so the loss changes by only
-            # ~1e-14 for a perturbation small enough to keep the O(eps^2)
-            # error of a two-point difference below 1e-6, where FP64 rounding
-            # of the forward run is already ~1e-6 of the change.  The
-            # four-point central difference (error O(eps^4)) allows a 3x
-            # larger step: both error sources fall well below the bound.
-            eps = 1e-3
-            fd = (8 * (loss_f(n, i, eps) - loss_f(n, i, -eps))
-                  - (loss_f(n, i, 2 * eps) - loss_f(n, i, -2 * eps))) / (12 * eps)
-            ad = gs.reshape(19, -1)[i, n]
-            rel = abs(fd - ad) / max(abs(fd), 1e-3 * smax)
-            log(f"   f node {n} i {i}: fd {fd:.10e} adjoint {ad:.10e} rel {rel:.2e}")
-            assert rel <= 1e-6
-    log(f"   L {L0:.6e}; worst g rel err {worst:.2e}")
+    worst_f = 0.0
+    for k, n in enumerate(nodes):
+        i = k % 19
+        # The f0 gradients are ~1e-11..1e-10, so the loss changes by only
+        # ~1e-14 per 1e-3 of perturbation, and the FP64 rounding of the
+        # perturbed forward runs (a different rounding path from the
+        # perturbation on) is ~1e-7 of that change: the error of a difference
+        # quotient falls with the step.  L depends on f through rho = sum f
+        # and j / rho, so its Taylor coefficients scale with 1 / rho ~ 1 and
+        # the six-point central difference (error ~ 36 eps^6 relative) at
+        # eps = 5e-3 is far below the bound while dividing the rounding noise
+        # by ~4 against a four-point difference at eps = 1e-3.
+        eps = 5e-3
+        fd = (45 * (loss_f(n, i, eps) - loss_f(n, i, -eps)) - 9 * (loss_f(n, i, 2 * eps) - loss_f(n, i, -2 * eps))
+              + (loss_f(n, i, 3 * eps) - loss_f(n, i, -3 * eps))) / (60 * eps)
+        ad = gs.reshape(19, -1)[i, n]
+        rel = abs(fd - ad) / max(abs(fd), 1e-3 * smax)
+        worst_f = max(worst_f, rel)
+        log(f"   f node {n} i {i}: fd {fd:.10e} adjoint {ad:.10e} rel {rel:.2e}")
+        assert rel <= 1e-6
+    log(f"   L {L0:.6e}; worst g rel err {worst:.2e}; worst f0 rel err {worst_f:.2e}")
 
 
 # FP32 storage and arithmetic (gradients still summed in FP64).  Each adjoint
@@ -210,9 +219,16 @@ def test_adjoint_f32_matches_oracle(periodic, K, K2, model):
     mi = O.MODELS[model]
     _, u = O.macroscopic(O.run(f0, sp, tau, T, force=g, periodic=periodic, model=mi), sp, force=g, model=mi)
     umax = np.abs(u[:, fl]).max()
-    log(f"   L {L:.9e} vs {Lo:.9e} (tol {tol * umax:.2e});  dL/ds0 err {es:.2e}  dL/dg err {eg:.2e}  tol {tol:.2e}")
+    # per entry: the same relative bound with an absolute floor at 1e-2 of the
+    # largest entry (FP32 rounding of a node's adjoint values scales with the
+    # largest values that node combines, not with each entry)
+    es_e = elementwise_err(gs, gs_o, fl, 1e-2)
+    eg_e = elementwise_err(gg, gF_o, fl, 1e-2)
+    log(f"   L {L:.9e} vs {Lo:.9e} (tol {tol * umax:.2e});  dL/ds0 err {es:.2e} (per entry {es_e:.2e})  "
+        f"dL/dg err {eg:.2e} (per entry {eg_e:.2e})  tol {tol:.2e}")
     assert abs(L - Lo) <= tol * umax
     assert es <= tol and eg <= tol
+    assert es_e <= tol and eg_e <= tol
     assert np.all(gs[:, ~fl] == 0) and np.all(gg[:, ~fl] == 0)
 
 
@@ -370,7 +386,7 @@ def test_adjoint_random_geometries(case):
     gs, gg = run.backward()
     gs, gg = gs.cpu().numpy(), gg.cpu().numpy()
     fl = sp == 0
-    es = np.max(np.abs(gs[:, fl] - gs_o[:, fl])) / np.abs(gs_o[:, fl]).max()
-    eg = np.max(np.abs(gg[:, fl] - gF_o[:, fl])) / np.abs(gF_o[:, fl]).max()
-    log(f"   dL/ds0 err {es:.2e}  dL/dg err {eg:.2e}")
-    assert es <= 1e-11 and eg <= 1e-11
+    es = elementwise_err(gs, gs_o, fl, F64_FLOOR)
+    eg = elementwise_err(gg, gF_o, fl, F64_FLOOR)
+    log(f"   per-entry dL/ds0 err {es:.2e}  dL/dg err {eg:.2e}")
+    assert es <= F64_TOL and eg <= F64_TOL
