@@ -133,8 +133,8 @@ typedef struct lbm_params {
     int32_t f32_unshifted;  /* LBM_F32 only: 1 stores f_i itself instead of f_i - w_i rho0 (the
                                paper's FP32 storage; kept as an ablation of the shift), 0 =
                                shifted (default).  Must be 0 for other storage types. */
-    int32_t check_u_max;    /* 1 = lbm_macroscopic, lbm_macroscopic_buf and lbm_permeability
-                               return LBM_E_NUMERIC (after filling their outputs)
+    int32_t check_u_max;    /* 1 = lbm_macroscopic, lbm_macroscopic_buf, lbm_macroscopic_noalloc
+                               and lbm_permeability return LBM_E_NUMERIC (after filling their outputs)
                                when the largest fluid speed max |u| exceeds LBM_U_MAX = 0.05, the
                                bound on the macroscopic velocity that keeps the compressibility
                                error of the quasi-compressible model small (Section 2.2);
@@ -251,6 +251,27 @@ int lbm_current_state(lbm_ctx *ctx, void **state);
 int lbm_macroscopic(lbm_ctx *ctx, double *rho_dev, double *u_dev, double sums[8]);
 /* The same for any lattice buffer of the context. */
 int lbm_macroscopic_buf(lbm_ctx *ctx, const void *state, double *rho_dev, double *u_dev, double sums[8]);
+
+/* lbm_macroscopic_buf for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the per-tile partial sums go to a library-owned device array
+ * instead of the context's scratch buffer, so this call needs no scratch and
+ * calls no hipMalloc, hipFree or allocating library routine.
+ *   state, rho_dev, u_dev, sums   as for lbm_macroscopic_buf (state NULL =
+ *                                 current lattice; rho_dev, u_dev may be NULL)
+ * The array holds the partials of at most LBM_NOALLOC_MAX_TILES kept tiles
+ * ((LBM_NOALLOC_MAX_TILES + 1) * 8 doubles, 16 MiB); it is part of the
+ * library's device code, so every GPU the library runs on holds its own copy
+ * until the process ends.  A context with more kept tiles gets LBM_E_RANGE
+ * (use lbm_macroscopic_buf).  Results are bitwise those of
+ * lbm_macroscopic_buf (same kernels, same reduction order), and the same
+ * LBM_E_NUMERIC checks apply.  Every call on one GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (from other streams, host
+ * threads or contexts) race and must be serialised by the caller.  The array
+ * keeps the last call's partials; nothing in it has to start at zero, since
+ * a call writes every entry it reads.  Synchronises the stream. */
+#define LBM_NOALLOC_MAX_TILES 262144
+int lbm_macroscopic_noalloc(lbm_ctx *ctx, const void *state, double *rho_dev, double *u_dev, double sums[8]);
 
 /* Darcy permeability of the current lattice along x: k = nu * q / g_x with the
  * superficial flux q = sum rho u_x / (rho0 * nx*ny*nz).  Synchronises. */

@@ -20,6 +20,7 @@ MODEL = {"qc": 0, "quasi-compressible": 0, "inc": 1, "incompressible": 1, "mrt-q
 EXPORTS = [
     "lbm_build_tiles", "lbm_tiles_free", "lbm_required_bytes", "lbm_create", "lbm_destroy", "lbm_init",
     "lbm_set_force", "lbm_set_boundaries", "lbm_step", "lbm_step_graphed", "lbm_step_buf", "lbm_current_state", "lbm_macroscopic", "lbm_macroscopic_buf",
+    "lbm_macroscopic_noalloc",
     "lbm_permeability", "lbm_get_state", "lbm_set_state", "lbm_tiles_to_dense", "lbm_adjoint_seed",
     "lbm_adjoint_step", "lbm_adjoint_final", "lbm_adjoint_get", "lbm_adjoint_set", "lbm_calib_step", "lbm_info",
     "lbm_last_error", "lbm_version",
@@ -85,6 +86,7 @@ def lib():
         "lbm_current_state": ([P, ctypes.POINTER(P)], ctypes.c_int),
         "lbm_macroscopic": ([P, P, P, P], ctypes.c_int),
         "lbm_macroscopic_buf": ([P, P, P, P, P], ctypes.c_int),
+        "lbm_macroscopic_noalloc": ([P, P, P, P, P], ctypes.c_int),
         "lbm_permeability": ([P, f64, ctypes.POINTER(f64)], ctypes.c_int),
         "lbm_get_state": ([P, P, P], ctypes.c_int),
         "lbm_set_state": ([P, P, P], ctypes.c_int),

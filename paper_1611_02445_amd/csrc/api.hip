@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -48,6 +49,8 @@ struct lbm_ctx {
     std::vector<int32_t> corner;  // [n_tiles][3] tile corners in device order (host copy)
     StepGraph graphs[2];          // lbm_step_graphed, by starting parity
     hipStream_t capture = nullptr;  // private stream the graphs are captured on
+    double *noalloc = nullptr;      // this device's copy of noalloc_scratch (lbm_macroscopic_noalloc)
+    hipError_t noalloc_err = hipSuccess;
     ~lbm_ctx() {
         graphs[0].release();
         graphs[1].release();
@@ -147,6 +150,34 @@ void processing_order(const lbm_tiles *t, int order, std::vector<int32_t> &perm)
     std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
 }
 
+// Reduction scratch of lbm_macroscopic_noalloc: the per-tile partials and
+// the final sums of up to LBM_NOALLOC_MAX_TILES tiles.  Host code never uses
+// this name as an address (on the host it is only a handle to the symbol):
+// each device's copy is looked up once with hipGetSymbolAddress and that
+// pointer is what the kernels get.
+static __device__ __align__(256) double noalloc_scratch[((size_t)LBM_NOALLOC_MAX_TILES + 1) * NSUM];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mutex;
+double *noalloc_ptr[NOALLOC_MAX_DEVICES];
+
+// the address of the current device's copy of noalloc_scratch, looked up on
+// the first call for that device (the caller has that device current)
+hipError_t noalloc_lookup(int device, double **out) {
+    *out = nullptr;
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(noalloc_mutex);
+    if (!noalloc_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        noalloc_ptr[device] = reinterpret_cast<double *>(p);
+    }
+    *out = noalloc_ptr[device];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *params, lbm_sizes *out) {
@@ -219,6 +250,9 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->state_bytes = lattice_elems(tiles, params->storage) * storage_size(params->storage);
     if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+    // set-up for lbm_macroscopic_noalloc, once per device with the context's
+    // device current; a failure is reported by that entry point only
+    c->noalloc_err = c->device >= 0 ? noalloc_lookup(c->device, &c->noalloc) : hipErrorNoDevice;
 
     const TableLayout lay(n);
     if (n > 0) {
@@ -507,26 +541,45 @@ static int check_sums(const lbm_ctx *c, const double *sums, const char *what) {
     return LBM_OK;
 }
 
-extern "C" int lbm_macroscopic_buf(lbm_ctx *c, const void *state, double *rho_dev, double *u_dev, double sums[8]) {
-    CHECK_CTX(c);
-    if (!sums) return fail(LBM_E_INVAL, "lbm_macroscopic: NULL sums");
+// the macroscopic fields and reduced sums of a lattice, with the per-tile
+// partials and the final sums in `partials` ([n_tiles + 1][8] doubles)
+static int macroscopic_into(lbm_ctx *c, const void *state, double *rho_dev, double *u_dev, double sums[8],
+                            double *partials) {
     if (!state) state = cur_state(c);
     const size_t N = (size_t)c->nx * c->ny * c->nz;
     hipError_t e = hipSuccess;
     if (rho_dev) e = launch_fill(c->stream, rho_dev, N);
     if (e == hipSuccess && u_dev) e = launch_fill(c->stream, u_dev, 3 * N);
-    double *final_ = c->scratch + (size_t)c->n_tiles * NSUM;
+    double *final_ = partials + (size_t)c->n_tiles * NSUM;
     if (c->n_tiles == 0) {
         for (int k = 0; k < NSUM; ++k) sums[k] = 0.0;
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         return launched(e, "lbm_macroscopic");
     }
-    if (e == hipSuccess) e = launch_macro(c->L, c->P, state, rho_dev, u_dev, c->nx, c->ny, c->nz, c->scratch);
-    if (e == hipSuccess) e = launch_reduce(c->stream, c->scratch, c->n_tiles, final_);
+    if (e == hipSuccess) e = launch_macro(c->L, c->P, state, rho_dev, u_dev, c->nx, c->ny, c->nz, partials);
+    if (e == hipSuccess) e = launch_reduce(c->stream, partials, c->n_tiles, final_);
     if (e == hipSuccess) e = hipMemcpyAsync(sums, final_, NSUM * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "lbm_macroscopic");
     return check_sums(c, sums, "lbm_macroscopic");
+}
+
+extern "C" int lbm_macroscopic_buf(lbm_ctx *c, const void *state, double *rho_dev, double *u_dev, double sums[8]) {
+    CHECK_CTX(c);
+    if (!sums) return fail(LBM_E_INVAL, "lbm_macroscopic: NULL sums");
+    return macroscopic_into(c, state, rho_dev, u_dev, sums, c->scratch);
+}
+
+extern "C" int lbm_macroscopic_noalloc(lbm_ctx *c, const void *state, double *rho_dev, double *u_dev, double sums[8]) {
+    CHECK_CTX(c);
+    if (!sums) return fail(LBM_E_INVAL, "lbm_macroscopic_noalloc: NULL sums");
+    if (c->n_tiles > LBM_NOALLOC_MAX_TILES)
+        return fail(LBM_E_RANGE, "lbm_macroscopic_noalloc: %d kept tiles exceed the %d of the static scratch "
+                                 "(use lbm_macroscopic_buf)", c->n_tiles, LBM_NOALLOC_MAX_TILES);
+    if (!c->noalloc)
+        return fail(LBM_E_HIP, "lbm_macroscopic_noalloc: static scratch unavailable on device %d: %s", c->device,
+                    hipGetErrorString(c->noalloc_err));
+    return macroscopic_into(c, state, rho_dev, u_dev, sums, c->noalloc);
 }
 
 extern "C" int lbm_macroscopic(lbm_ctx *c, double *rho_dev, double *u_dev, double sums[8]) {
