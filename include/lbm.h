@@ -351,6 +351,22 @@ int lbm_adjoint_set(lbm_ctx *ctx, const double *dense_dev, void *adj);
  * ------------------------------------------------------------------------ */
 int lbm_calib_step(lbm_ctx *ctx, int32_t kind, const void *src, void *dst);
 
+/* Bandwidth probes: plain streaming kernels that measure what the GPU
+ * sustains, the practical ceiling read beside the nominal HBM peak (the
+ * paper sets its GPU's measured copy bandwidth beside the peak, Section 4.1).
+ *   kind 1 read only: reads `bytes` of src; dst receives at most 4 bytes,
+ *          and only when the data hash to one fixed value (which keeps the
+ *          loads), so it needs 16 writable bytes
+ *   kind 2 write only: writes zeros over `bytes` of dst; src may be NULL
+ *   kind 3 copy: dst = src over `bytes`; the ranges must not overlap
+ * 16-byte non-temporal loads and stores, four in flight per thread, grid-stride
+ * over the buffer with `blocks` workgroups (1 .. 2^20) of `threads` threads
+ * (64, 128, 256, 512 or 1024).  bytes must be a positive multiple of 16 and
+ * both buffers 16-byte aligned (else LBM_E_INVAL).  Needs no context;
+ * asynchronous on hip_stream (NULL = the default stream). */
+int lbm_stream_probe(void *hip_stream, int32_t kind, const void *src, void *dst, size_t bytes, int32_t blocks,
+                     int32_t threads);
+
 /* Counts of the current context (any pointer may be NULL). */
 int lbm_info(lbm_ctx *ctx, int32_t *n_tiles, int64_t *n_fluid, int32_t *storage, int32_t *grid_blocks);
 

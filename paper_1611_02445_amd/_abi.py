@@ -22,7 +22,8 @@ EXPORTS = [
     "lbm_set_force", "lbm_set_boundaries", "lbm_step", "lbm_step_graphed", "lbm_step_buf", "lbm_current_state", "lbm_macroscopic", "lbm_macroscopic_buf",
     "lbm_macroscopic_noalloc",
     "lbm_permeability", "lbm_get_state", "lbm_set_state", "lbm_tiles_to_dense", "lbm_adjoint_seed",
-    "lbm_adjoint_step", "lbm_adjoint_final", "lbm_adjoint_get", "lbm_adjoint_set", "lbm_calib_step", "lbm_info",
+    "lbm_adjoint_step", "lbm_adjoint_final", "lbm_adjoint_get", "lbm_adjoint_set", "lbm_calib_step",
+    "lbm_stream_probe", "lbm_info",
     "lbm_last_error", "lbm_version",
 ]
 
@@ -97,6 +98,7 @@ def lib():
         "lbm_adjoint_get": ([P, P, P], ctypes.c_int),
         "lbm_adjoint_set": ([P, P, P], ctypes.c_int),
         "lbm_calib_step": ([P, i32, P, P], ctypes.c_int),
+        "lbm_stream_probe": ([P, i32, P, P, ctypes.c_size_t, i32, i32], ctypes.c_int),
         "lbm_info": ([P, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)],
                      ctypes.c_int),
         "lbm_last_error": ([], ctypes.c_char_p),

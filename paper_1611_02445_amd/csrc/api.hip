@@ -698,6 +698,25 @@ extern "C" int lbm_calib_step(lbm_ctx *c, int32_t kind, const void *src, void *d
     return launched(launch_calib(c->L, kind, c->params.storage, src, dst), "lbm_calib_step");
 }
 
+extern "C" int lbm_stream_probe(void *hip_stream, int32_t kind, const void *src, void *dst, size_t bytes,
+                                int32_t blocks, int32_t threads) {
+    clear_error();
+    if (kind < 1 || kind > 3) return fail(LBM_E_INVAL, "lbm_stream_probe: kind must be 1 (read), 2 (write) or 3 (copy)");
+    if (bytes == 0 || bytes % 16) return fail(LBM_E_INVAL, "lbm_stream_probe: bytes must be a positive multiple of 16");
+    if (blocks < 1 || blocks > (1 << 20)) return fail(LBM_E_INVAL, "lbm_stream_probe: blocks must be in 1..2^20");
+    if (!(threads == 64 || threads == 128 || threads == 256 || threads == 512 || threads == 1024))
+        return fail(LBM_E_INVAL, "lbm_stream_probe: threads must be 64, 128, 256, 512 or 1024");
+    if ((kind != 2 && !src) || !dst) return fail(LBM_E_INVAL, "lbm_stream_probe: NULL buffer");
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16)
+        return fail(LBM_E_INVAL, "lbm_stream_probe: buffers must be 16-byte aligned");
+    if (kind == 3) {
+        const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+        if (a < b + bytes && b < a + bytes) return fail(LBM_E_INVAL, "lbm_stream_probe: src and dst overlap");
+    }
+    return launched(launch_probe(reinterpret_cast<hipStream_t>(hip_stream), kind, src, dst, bytes, blocks, threads),
+                    "lbm_stream_probe");
+}
+
 extern "C" int lbm_info(lbm_ctx *c, int32_t *n_tiles, int64_t *n_fluid, int32_t *storage, int32_t *grid_blocks) {
     CHECK_CTX(c);
     if (n_tiles) *n_tiles = c->n_tiles;

@@ -1296,6 +1296,63 @@ __global__ __launch_bounds__(512) void k_adj_final(AdjArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// bandwidth probes: what the part sustains for plain streaming, the practical
+// ceiling beside the nominal peak (the paper sets its GPU's measured copy
+// bandwidth beside the peak, Section 4.1).  Kind 1 reads, kind 2 writes zeros,
+// kind 3 copies; 16-byte non-temporal accesses, PROBE_UNROLL of them in
+// flight per thread, grid-stride over the buffer.
+// ---------------------------------------------------------------------------
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int PROBE_UNROLL = 4;
+
+template <int KIND>
+__global__ __launch_bounds__(1024) void k_probe(const u32x4 *src, u32x4 *dst, size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    for (; i + (PROBE_UNROLL - 1) * stride < n16; i += PROBE_UNROLL * stride) {
+        u32x4 v[PROBE_UNROLL];
+        if constexpr (KIND != 2) {
+#pragma unroll
+            for (int u = 0; u < PROBE_UNROLL; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+        }
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; ++u) {
+            if constexpr (KIND == 1) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+            else if constexpr (KIND == 2) __builtin_nontemporal_store(u32x4{0u, 0u, 0u, 0u}, dst + i + u * stride);
+            else __builtin_nontemporal_store(v[u], dst + i + u * stride);
+        }
+    }
+    for (; i < n16; i += stride) {
+        if constexpr (KIND == 1) {
+            const u32x4 v = __builtin_nontemporal_load(src + i);
+            acc ^= v.x ^ v.y ^ v.z ^ v.w;
+        } else if constexpr (KIND == 2) {
+            __builtin_nontemporal_store(u32x4{0u, 0u, 0u, 0u}, dst + i);
+        } else {
+            __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+        }
+    }
+    // the read probe stores only if its data hash to one fixed value, which
+    // keeps every load without writing anything in practice
+    if constexpr (KIND == 1) {
+        if (acc == 0x9E3779B9u) reinterpret_cast<uint32_t *>(dst)[0] = acc;
+    }
+}
+
+hipError_t launch_probe(hipStream_t s, int kind, const void *src, void *dst, size_t bytes, int blocks, int threads) {
+    const u32x4 *in = reinterpret_cast<const u32x4 *>(src);
+    u32x4 *out = reinterpret_cast<u32x4 *>(dst);
+    const size_t n16 = bytes / 16;
+    switch (kind) {
+    case 1: hipLaunchKernelGGL(k_probe<1>, dim3(blocks), dim3(threads), 0, s, in, out, n16); break;
+    case 2: hipLaunchKernelGGL(k_probe<2>, dim3(blocks), dim3(threads), 0, s, in, out, n16); break;
+    default: hipLaunchKernelGGL(k_probe<3>, dim3(blocks), dim3(threads), 0, s, in, out, n16); break;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static KArgs make_args(const Launch &L, const Phys &P, const void *src, void *dst) {

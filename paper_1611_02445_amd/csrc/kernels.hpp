@@ -52,6 +52,7 @@ hipError_t launch_tiles_to_dense(const Launch &L, const void *tile_buf, int ncom
 hipError_t launch_adjoint_seed(const Launch &L, const Phys &P, const void *s_prev, void *eta, double *grad);
 hipError_t launch_adjoint_step(const Launch &L, const Phys &P, const void *s_prev2, const void *eta_in,
                                void *eta_out, double *grad);
+hipError_t launch_probe(hipStream_t s, int kind, const void *src, void *dst, size_t bytes, int blocks, int threads);
 hipError_t launch_adjoint_final(const Launch &L, const Phys &P, const void *eta_in, void *lambda_out);
 
 }  // namespace tlbm

@@ -112,3 +112,24 @@ def test_compressibility_limit_is_the_papers():
     t = Tiling(np.zeros((8, 8, 8), np.uint8), 7)
     sz = _abi.Sizes()
     assert _abi.lib().lbm_required_bytes(t._ptr, ctypes.byref(_params(check_u_max=1)), ctypes.byref(sz)) == 0
+
+
+@pytest.mark.parametrize("kind,nbytes,blocks,threads", [(0, 1024, 64, 256), (4, 1024, 64, 256), (3, 1000, 64, 256),
+                                                        (3, 0, 64, 256), (3, 1024, 0, 256), (3, 1024, 1 << 21, 256),
+                                                        (3, 1024, 64, 100), (3, 1024, 64, 2048)])
+def test_stream_probe_validation(kind, nbytes, blocks, threads):
+    """Arguments are checked before anything is launched: the addresses below
+    are never dereferenced."""
+    src, dst = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)
+    assert _abi.lib().lbm_stream_probe(None, kind, src, dst, nbytes, blocks, threads) == -1
+    assert _abi.lib().lbm_last_error().startswith(b"lbm_stream_probe")
+
+
+def test_stream_probe_rejects_overlap_and_misalignment():
+    base = 1 << 20
+    L = _abi.lib()
+    assert L.lbm_stream_probe(None, 3, ctypes.c_void_p(base), ctypes.c_void_p(base + 512), 1024, 8, 64) == -1
+    assert b"overlap" in L.lbm_last_error()
+    assert L.lbm_stream_probe(None, 3, ctypes.c_void_p(base + 8), ctypes.c_void_p(1 << 30), 1024, 8, 64) == -1
+    assert b"aligned" in L.lbm_last_error()
+    assert L.lbm_stream_probe(None, 1, None, ctypes.c_void_p(1 << 30), 1024, 8, 64) == -1
