@@ -10,9 +10,14 @@ from paper_1611_02445_amd import inputs as I
 
 from helpers import elementwise_err, log, new_lattice, padded, perturbed_state
 
-# FP64 adjoint against the oracle's: every entry within 1e-11 relative, an
-# entry smaller than 1e-6 of the largest one measured against that floor
-F64_TOL, F64_FLOOR = 1e-11, 1e-6
+# FP64 adjoint against the oracle's, entry by entry: within 1e-11 relative
+# for every entry above 1e-3 of the largest one, within 1e-14 of the largest
+# below that.  An entry is a sum of contributions as large as the largest
+# entries, so its FP64 rounding is absolute, a few ulp of the largest values
+# (max-normalised differences of ~1e-15 after 12 steps); a floor at 1e-6 of
+# the largest entry would ask for less than one ulp of it (3e-17 of it was
+# seen on a near-zero entry).
+F64_TOL, F64_FLOOR = 1e-11, 1e-3
 
 pytestmark = pytest.mark.gpu
 
