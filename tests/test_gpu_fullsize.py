@@ -38,3 +38,40 @@ def test_sphere_pack_256_sampled_nodes_and_mass(model):
     assert err <= 1e-12
     assert abs(s1[0] - s0[0]) / s0[0] <= 1e-13
     assert s1[4] == lat.n_fluid and s1[6] == 0
+
+
+def test_sphere_pack_256_permeability_matches_oracle_golden():
+    """The whole-box permeability, mass and momentum of the 256^3 pack after
+    the same number of steps as the oracle's full-size run (FP64, tau 0.7,
+    g_x 1e-6, from rest; tests/golden/spheres256_oracle.json, written by the
+    oracle alone).
+
+    Bounds follow from the per-distribution FP64 bar (1e-12 relative): a
+    momentum component sum_nodes sum_i c_ia f_i then differs by at most
+    1e-12 sum_nodes sum_i |c_ia| f_i = 1e-12 n_fluid rho0 / 3 (sum_i |c_ia| w_i
+    = 1/3, and f stays within 1e-4 of rest here), and k is proportional to
+    the x-momentum.  Mass is conserved exactly in exact arithmetic by both
+    sides: 1e-13 relative, as for the mass drift."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "spheres256_oracle.json")))
+    tau, g = gold["tau"], gold["g_x"]
+    s, n_sph = I.sphere_pack((256, 256, 256), 0.4, 4.0, 12.0, seed=2)
+    assert n_sph == gold["spheres"]
+    lat = new_lattice(s, tau, 7)
+    lat.init()
+    lat.set_force((g, 0, 0))
+    lat.step(gold["steps"])
+    k = lat.permeability(g)
+    _, _, sums = lat.macroscopic(fields=False)
+    mom_bound = 1e-12 * lat.n_fluid / 3.0
+    rel_k = abs(k - gold["permeability"]) / abs(gold["permeability"])
+    log(f"[case] spheres256 after {gold['steps']} steps: k {k:.15e} oracle {gold['permeability']:.15e} "
+        f"rel {rel_k:.2e} (bound {mom_bound / abs(gold['momentum'][0]):.2e}); momentum diff "
+        f"{[float(sums[a] - gold['momentum'][a - 1]) for a in (1, 2, 3)]} (bound {mom_bound:.2e}); "
+        f"mass diff {sums[0] - gold['mass']:.3e}")
+    assert sums[4] == gold["n_fluid"] == lat.n_fluid
+    assert rel_k <= mom_bound / abs(gold["momentum"][0])
+    assert abs(sums[0] - gold["mass"]) <= 1e-13 * gold["mass"]
+    for a in (1, 2, 3):
+        assert abs(sums[a] - gold["momentum"][a - 1]) <= mom_bound
