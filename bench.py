@@ -10,9 +10,11 @@ region holds exactly --steps steps with the lattice resident in HBM.
 
 Prints one JSON line: MFLUPS (million fluid-node updates per second), the
 roofline of the step kernel (algorithmic bytes per launch / average launch
-time, against 8 TB/s), the CPU oracle timed on a bounded sample of the same
-workload, permeability after the run, and the FP32 / FP16-shifted storage
-variants with their errors against the FP64 result.
+time, against 8 TB/s and against the copy bandwidth the streaming probes
+measure first), the CPU oracle timed on a bounded sample of the same
+workload (all host threads and one), permeability after the run, and the
+FP32 / FP16-shifted storage variants with their errors against the FP64
+result, stated on a fixed run of --error-steps steps from rest.
 """
 import argparse
 import json
@@ -81,8 +83,9 @@ def time_storage(solid, storage, args, torch, want_state=False, model="qc"):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
-    # per-launch spread (the paper times every launch separately)
-    nlaunch = min(100, args.steps)
+    # per-launch spread over a fixed number of separately timed launches (the
+    # paper times every launch separately), whatever --steps is
+    nlaunch = 500
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(nlaunch + 1)]
     evs[0].record(stream)
     for k in range(nlaunch):
@@ -517,26 +520,155 @@ def sweep_channels(args, torch):
                                         "per_face": round(float(coef[1]), 5), "per_edge": round(float(coef[2]), 5)}}
 
 
-def cpu_baseline(solid, args):
-    """The oracle as it stands, on the same geometry, for a bounded number of
-    steps (about --cpu-seconds of CPU work)."""
+def fp64_state_bytes(solid, args):
+    import ctypes
+    from paper_1611_02445_amd import _abi
+    from paper_1611_02445_amd.lattice import Tiling
+    t = Tiling(solid, 7)
+    p = _abi.Params(tau=args.tau, rho0=1.0, storage=0, model=0, f16_log2_scale=20)
+    sz = _abi.Sizes()
+    _abi.call("lbm_required_bytes", t._ptr, ctypes.byref(p), ctypes.byref(sz))
+    return sz.state_bytes
+
+
+def probe_ceiling(nbytes, torch, launches=10):
+    """What the GPU sustains for plain streaming over one lattice's bytes: the
+    library's read-only, write-only and copy probes (16-byte non-temporal
+    accesses) over a sweep of workgroup counts and sizes; the best rate of
+    each (copy counted as bytes read + bytes written)."""
+    import ctypes
+    from paper_1611_02445_amd import _abi
+    n = nbytes // 16 * 16
+    a = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    pa, pb = ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr())
+    best = {}
+    rows = []
+    for kind, name, moved in ((1, "read", n), (2, "write", n), (3, "copy", 2 * n)):
+        for threads in (256, 512, 1024):
+            for blocks in (2048, 8192, 32768, 65536, 131072, 262144):
+                def go():
+                    _abi.call("lbm_stream_probe", sp, kind, pa, pb, n, blocks, threads)
+                for _ in range(3):
+                    go()
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record(stream)
+                for _ in range(launches):
+                    go()
+                ev1.record(stream)
+                torch.cuda.synchronize()
+                ms = ev0.elapsed_time(ev1) / launches
+                gbs = moved / (ms / 1e3) / 1e9
+                rows.append((name, threads, blocks, round(ms * 1e3, 2), round(gbs, 1)))
+                if gbs > best.get(name, {}).get("GBs", 0.0):
+                    best[name] = {"GBs": round(gbs, 1), "us": round(ms * 1e3, 2), "threads": threads,
+                                  "blocks": blocks}
+    del a, b
+    for name in ("read", "write", "copy"):
+        log(f"[bench] probe {name}: {best[name]['GBs']:.0f} GB/s ({best[name]['threads']} x {best[name]['blocks']})")
+    return {"bytes": n, "best": best, "peak_frac": {k: round(v["GBs"] / HBM_PEAK_GBS, 4) for k, v in best.items()},
+            "sweep": rows}
+
+
+def error_run(solid, args, torch, variants):
+    """The stated error of the reduced-precision storage types: FP64 and each
+    variant run from rest for --error-steps steps on the same geometry
+    (tau, g_x as the timed run); permeability and velocity of each against
+    the FP64 run, whose step the parity tests hold to the oracle node by
+    node.  The FP64 permeability at half the steps shows how close the run
+    is to steady flow."""
+    from paper_1611_02445_amd.lattice import Lattice
+    n = args.error_steps
+    out = {"steps": n, "reference": "GPU FP64 on the same run (node-by-node oracle parity is tested)"}
+    u64 = None
+    for st in ["f64"] + [v for v in variants if v != "f64"]:
+        lat = Lattice(solid, args.tau, periodic=7, storage="f32" if st == "f32u" else st,
+                      tiles_per_wg=args.tpw, tile_order=args.order, f32_unshifted=st == "f32u", check_u_max=True)
+        lat.init()
+        lat.set_force((args.g, 0.0, 0.0))
+        lat.step(n // 2)
+        k_half = lat.permeability(args.g)
+        lat.step(n - n // 2)
+        k = lat.permeability(args.g)
+        _, u, sums = lat.macroscopic()
+        if u64 is None:
+            u64, k64, m64 = u, k, sums[0]
+            out["f64"] = {"permeability": k, "permeability_at_half_steps": k_half,
+                          "rel_change_over_second_half": abs(k - k_half) / abs(k), "u_max": sums[5]}
+            log(f"[bench] error run f64: k {k:.6e} (half-way {k_half:.6e})")
+        else:
+            du = torch.linalg.vector_norm(u - u64).item() / torch.linalg.vector_norm(u64).item()
+            dk = abs(k - k64) / abs(k64)
+            out[st] = {"permeability": k, "rel_permeability_err_vs_f64": dk, "rel_l2_velocity_vs_f64": du,
+                       "mass_drift": (sums[0] - m64) / m64, "u_max": sums[5]}
+            log(f"[bench] error run {st}: |dk|/k {dk:.2e}, |du|/|u| {du:.2e}")
+            del u
+        del lat
+        torch.cuda.empty_cache()
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample(solid, args, seconds, max_steps=200):
+    """The oracle as it stands, dense FP64 steps of the same geometry, for about
+    `seconds` of CPU time: (MFLUPS, steps, seconds used, threads, fluid nodes)."""
     import oracle as O
     from oracle import tiles_ref
     sp = tiles_ref.pad(solid, 7)
     f = O.init(sp)
-    scratch = np.zeros_like(f)
     nf = int((sp == 0).sum())
     O.step(f[:, :4, :4, :4], sp[:4, :4, :4], args.tau)  # load + build
     steps, t_used = 0, 0.0
-    while t_used < args.cpu_seconds and steps < 200:
+    while (t_used < seconds or steps == 0) and steps < max_steps:
         t0 = time.perf_counter()
         f = O.step(f, sp, args.tau, force=[args.g, 0.0, 0.0], periodic=7)
         t_used += time.perf_counter() - t0
         steps += 1
-    del scratch
-    return dict(value=nf * steps / t_used / 1e6, unit="MFLUPS", cores=O.num_threads(), kind="oracle",
-                sample=f"{steps} dense FP64 steps of the same {args.n}^3 sphere pack ({nf} fluid nodes), "
-                       f"{t_used:.1f} s")
+    return nf * steps / t_used / 1e6, steps, t_used, O.num_threads(), nf
+
+
+def cpu_baseline(solid, args):
+    """The oracle as it stands, on the same geometry, for a bounded number of
+    steps (about --cpu-seconds of CPU work) on all host threads, then on one
+    thread (a child process with OMP_NUM_THREADS=1, about --cpu-seconds-one)."""
+    import subprocess
+    mf, steps, t_used, threads, nf = _oracle_sample(solid, args, args.cpu_seconds)
+    out = dict(value=mf, unit="MFLUPS", cores=threads, kind="oracle",
+               sample=f"{steps} dense FP64 steps of the same {args.n}^3 sphere pack ({nf} fluid nodes), "
+                      f"{t_used:.1f} s", cpu_model=_cpu_model(), host_cpus=os.cpu_count())
+    if args.cpu_seconds_one > 0:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-one-core-leg", "--n", str(args.n),
+               "--porosity", str(args.porosity), "--seed", str(args.seed), "--tau", str(args.tau),
+               "--g", str(args.g), "--cpu-seconds", str(args.cpu_seconds_one)]
+        r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode == 0:
+            one = json.loads(r.stdout.strip().splitlines()[-1])
+            out["one_core"] = one
+        else:
+            out["one_core"] = {"error": r.stderr.strip()[-300:]}
+    return out
+
+
+def one_core_leg(args):
+    """Child process of cpu_baseline: the oracle on one thread."""
+    solid = build_case(args)
+    mf, steps, t_used, threads, nf = _oracle_sample(solid, args, args.cpu_seconds)
+    print(json.dumps(dict(value=mf, unit="MFLUPS", cores=threads, kind="oracle",
+                          sample=f"{steps} dense FP64 steps of the same {args.n}^3 sphere pack ({nf} fluid nodes), "
+                                 f"{t_used:.1f} s on one thread")), flush=True)
 
 
 def main():
@@ -552,7 +684,14 @@ def main():
     ap.add_argument("--tpw", type=int, default=0, help="tiles per workgroup (0 = library default)")
     ap.add_argument("--order", type=int, default=0, help="device tile order (0 = library default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds-one", type=float, default=10.0,
+                    help="seconds of the one-thread oracle sample (0 = skip it)")
+    ap.add_argument("--cpu-one-core-leg", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--error-steps", type=int, default=10000,
+                    help="steps of the fixed run the storage variants' errors are stated on (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ceiling", dest="ceiling", action="store_false",
+                    help="skip the streaming-probe sweep (the measured bandwidth ceiling)")
     ap.add_argument("--variants", default="f32,f16s,f32u",
                     help="extra storage variants ('' for none); f32u = FP32 without the shift (ablation)")
     ap.add_argument("--kernel", default="step", choices=["step", "rw", "prop"],
@@ -572,6 +711,9 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
+    if args.cpu_one_core_leg:
+        one_core_leg(args)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
@@ -604,7 +746,10 @@ def main():
         print(json.dumps(time_calib(solid, args, torch)), flush=True)
         return
 
-    r = time_storage(solid, "f64", args, torch, want_state=bool(args.variants))
+    # the streaming ceiling over one FP64 lattice's bytes (it also brings the
+    # GPU to its working clocks before the timed step)
+    ceiling = probe_ceiling(fp64_state_bytes(solid, args), torch) if args.ceiling else None
+    r = time_storage(solid, "f64", args, torch)
     lat = r["lat"]
     nf = lat.n_fluid
     ms_per_step = r["gpu_ms"] / args.steps
@@ -662,26 +807,14 @@ def main():
     }
     if traffic is not None:
         result["roofline"]["traffic_bytes_per_fluid_update"] = round(traffic / nf, 1)
-    # a plain device copy of one lattice's size: what the part sustains for
-    # equal read and write traffic, as context for the 8 TB/s peak
-    nb = lat.sizes.state_bytes // 8
-    ca = torch.ones(nb, dtype=torch.float64, device="cuda")
-    cb = torch.empty_like(ca)
-    cb.copy_(ca)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(20):
-        cb.copy_(ca)
-    ev1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2 * nb * 8 / (ev0.elapsed_time(ev1) / 20 / 1e3) / 1e9
-    del ca, cb
-    result["copy_ceiling"] = {"read_plus_write_GBs": round(copy_gbs, 1), "bytes_each_way": nb * 8,
-                              "step_algorithmic_frac_of_copy": round(achieved / copy_gbs, 4)}
-    log(f"[bench] device copy {copy_gbs:.0f} GB/s read+write; step at {achieved / copy_gbs:.3f} of it")
-    # the paper's measurement kernels on the same tiles: the practical ceiling
-    # of this layout (read/write only) and the cost of the gather alone
+    if ceiling is not None:
+        # the best plain copy over the same number of bytes: the practical
+        # ceiling for equal read and write traffic
+        result["roofline"]["ceiling_GBs"] = ceiling["best"]["copy"]["GBs"]
+        result["roofline"]["frac_of_ceiling"] = round(achieved / ceiling["best"]["copy"]["GBs"], 4)
+        result["bandwidth_probe"] = ceiling
+    # the paper's measurement kernels on the same tiles: what this layout
+    # sustains without any gather (read/write only) and the gather alone
     result["paper_kernels"] = {}
     for kname in ("rw", "prop"):
         c = time_calib(solid, args, torch, kernel=kname, launches=min(args.steps, 500), lat=lat)
@@ -691,22 +824,27 @@ def main():
 
     variants = {}
     for st in [v for v in args.variants.split(",") if v]:
-        rv = time_storage(solid, st, args, torch, want_state=True)
+        rv = time_storage(solid, st, args, torch)
         ms = rv["gpu_ms"] / args.steps
         mf = nf * args.steps / (rv["gpu_ms"] / 1e3) / 1e6
-        u64, uv = r["u"], rv["u"]
-        du = torch.linalg.vector_norm(uv - u64).item() / torch.linalg.vector_norm(u64).item()
-        dk = abs(rv["k"] - r["k"]) / abs(r["k"])
         tr = counter_traffic(f"step_{st}_spheres256")
         variants[st] = {"MFLUPS": round(mf, 2), "ms_per_step": round(ms, 6),
+                        "launch_ms_mean": round(float(rv["per"].mean()), 4),
                         "traffic_GBs": None if tr is None else round(tr / (ms / 1e3) / 1e9, 1),
                         "gain_over_f64": round(mf / mflups, 3),
                         "hbm_frac": round(BYTES_PER_UPDATE[st] * nf / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                        "bytes_per_fluid_update": BYTES_PER_UPDATE[st],
-                        "rel_l2_velocity_vs_f64": du, "rel_permeability_err_vs_f64": dk,
-                        "mass_drift": (rv["sums"][0] - r["sums"][0]) / r["sums"][0]}
-        log(f"[bench] {st}: {mf:.1f} MFLUPS (x{mf / mflups:.2f}), |du|/|u| {du:.2e}, dk/k {dk:.2e}")
+                        "bytes_per_fluid_update": BYTES_PER_UPDATE[st]}
+        log(f"[bench] {st}: {mf:.1f} MFLUPS (x{mf / mflups:.2f})")
         del rv
+    if variants and args.error_steps > 0:
+        # the stated error of each storage type: a fixed run from rest,
+        # independent of --steps
+        err = error_run(solid, args, torch, list(variants))
+        result["error_run"] = err
+        for st in variants:
+            variants[st].update({k: err[st][k] for k in ("rel_permeability_err_vs_f64", "rel_l2_velocity_vs_f64",
+                                                         "mass_drift")})
+            variants[st]["error_steps"] = err["steps"]
     if variants:
         result["variants"] = variants
     # the paper's LBMRT kernels: multiple relaxation times, same tiles and bytes
