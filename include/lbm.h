@@ -22,6 +22,11 @@
  *     (the XYZ map, Eq. 11);
  *   - tile-order buffers are [n_tiles][components][64], tiles in the
  *     context's device order (see tile_order); lbm_tiles_to_dense converts;
+ *   - per-node fields (the force density and its gradient) hold one entry per
+ *     fluid node and component: tile t's run of 3k entries (k fluid nodes),
+ *     component c of the node with rank r among the tile's fluid nodes (in
+ *     node order n = x + 4y + 16z) at entry c*k + r, padded to a multiple of
+ *     16 entries, tiles in device order; lbm_field_to_dense converts;
  *   - device pointers are plain HIP device addresses owned by the caller; the
  *     library allocates no device buffers (lbm_step_graphed alone creates a
  *     private stream and executable graphs, held by the context until
@@ -149,9 +154,10 @@ typedef struct lbm_sizes {
                                 128-byte lines (FP64, FP32); n_tiles * 19 * 64 * 2 (FP16) */
     size_t table_bytes;      /* device copy of the tiling tables */
     size_t scratch_bytes;    /* reduction scratch */
-    size_t force_bytes;      /* per-node force field in tile order: n_tiles * 3 * 64 * sizeof(arith) */
+    size_t force_bytes;      /* per-node force field: sum over tiles of 3k padded to 16 entries,
+                                times sizeof(arith) (FP64 storage: 8, else 4) */
     size_t adjoint_bytes;    /* one adjoint lattice: state_bytes (FP64, FP32), 0 for FP16 */
-    size_t grad_force_bytes; /* force gradient, FP64: n_tiles * 3 * 64 * 8 */
+    size_t grad_force_bytes; /* force gradient, FP64, same entries as the force field: entries * 8 */
     size_t bc_bytes;         /* open boundaries: n_tiles * 72 (node mask + 64 node codes) */
     size_t dense_nodes;      /* nx * ny * nz of the padded box */
 } lbm_sizes;
@@ -285,6 +291,11 @@ int lbm_get_state(lbm_ctx *ctx, const void *state, double *f_dense_dev);
  * solid slots are set to 0).  state == NULL means the current lattice. */
 int lbm_set_state(lbm_ctx *ctx, const double *f_dense_dev, void *state);
 
+/* A per-node field (force density or force gradient; see the conventions)
+ * of FP64 (dtype 0) or FP32 (dtype 1) to a dense FP64 [3][nz][ny][nx] device
+ * array (0 at solid and dropped nodes). */
+int lbm_field_to_dense(lbm_ctx *ctx, const void *field_buf, int32_t dtype, double *dense_dev);
+
 /* Tile-order buffer [n_tiles][ncomp][64] of FP64 (dtype 0) or FP32 (dtype 1)
  * to a dense FP64 [ncomp][nz][ny][nx] device array (0 outside kept tiles). */
 int lbm_tiles_to_dense(lbm_ctx *ctx, const void *tile_buf, int32_t ncomp, int32_t dtype, double *dense_dev);
@@ -303,7 +314,8 @@ int lbm_tiles_to_dense(lbm_ctx *ctx, const void *tile_buf, int32_t ncomp, int32_
  * The adjoint lattices hold eta_t = J_t^T lambda_t (J_t = dC/dg at
  * g_t = S s_{t-1}, lambda_t = dL/ds_t); lambda_{t-1} = S^T eta_t is formed
  * on the fly by a reverse gather.  Gradients with respect to the body
- * acceleration g are accumulated in FP64 tile order [n_tiles][3][64].
+ * acceleration g are accumulated in FP64 per-node-field order (one entry
+ * per fluid node and component, see the conventions; lbm_field_to_dense).
  * The backward sweep is:
  *     lbm_adjoint_seed(s_{T-1})                      -> eta_T,  gF  = ...
  *     lbm_adjoint_step(s_{t-2}, eta_t) for t=T..2   -> eta_{t-1}, gF += ...

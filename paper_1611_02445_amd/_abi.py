@@ -21,7 +21,8 @@ EXPORTS = [
     "lbm_build_tiles", "lbm_tiles_free", "lbm_required_bytes", "lbm_create", "lbm_destroy", "lbm_init",
     "lbm_set_force", "lbm_set_boundaries", "lbm_step", "lbm_step_graphed", "lbm_step_buf", "lbm_current_state", "lbm_macroscopic", "lbm_macroscopic_buf",
     "lbm_macroscopic_noalloc",
-    "lbm_permeability", "lbm_get_state", "lbm_set_state", "lbm_tiles_to_dense", "lbm_adjoint_seed",
+    "lbm_permeability", "lbm_get_state", "lbm_set_state", "lbm_tiles_to_dense", "lbm_field_to_dense",
+    "lbm_adjoint_seed",
     "lbm_adjoint_step", "lbm_adjoint_final", "lbm_adjoint_get", "lbm_adjoint_set", "lbm_calib_step",
     "lbm_stream_probe", "lbm_info",
     "lbm_last_error", "lbm_version",
@@ -92,6 +93,7 @@ def lib():
         "lbm_get_state": ([P, P, P], ctypes.c_int),
         "lbm_set_state": ([P, P, P], ctypes.c_int),
         "lbm_tiles_to_dense": ([P, P, i32, i32, P], ctypes.c_int),
+        "lbm_field_to_dense": ([P, P, i32, P], ctypes.c_int),
         "lbm_adjoint_seed": ([P, P, P, P], ctypes.c_int),
         "lbm_adjoint_step": ([P, P, P, P, P], ctypes.c_int),
         "lbm_adjoint_final": ([P, P, P], ctypes.c_int),

@@ -231,7 +231,8 @@ class CheckpointedAdjoint:
     def backward(self, dense=True):
         """Reverse sweep; returns (dL/ds0 dense [19,...], dL/dg dense [3,...]),
         or with dense=False the library's own buffers: the adjoint lattice
-        holding dL/ds0 and the FP64 tile-order gradient [n_tiles, 3, 64]."""
+        holding dL/ds0 and the FP64 gradient in per-node-field order (one
+        entry per fluid node and component; lattice.field_to_dense)."""
         lat = self.lat
         e_cur, e_nxt = self.eta
         # states needed, in order: s_{T-1} (seed), s_{T-2}, ..., s_0 (steps t = T..2)
@@ -245,9 +246,9 @@ class CheckpointedAdjoint:
                 e_cur, e_nxt = e_nxt, e_cur
         lat.adjoint_final(e_cur, e_nxt)
         if not dense:
-            return e_nxt, self.grad.view(-1, 3, 64)
+            return e_nxt, self.grad
         g_f0 = lat.adjoint_get(e_nxt)
-        g_g = lat.tiles_to_dense(self.grad, 3, 0)
+        g_g = lat.field_to_dense(self.grad, 0)
         return g_f0, g_g
 
 

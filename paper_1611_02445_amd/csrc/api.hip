@@ -62,6 +62,13 @@ namespace {
 
 size_t arith_size(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
+// entries of one per-node field (force density or its gradient)
+uint64_t field_entries(const lbm_tiles *t) {
+    uint64_t e = 0;
+    for (int64_t i = 0; i < t->n_tiles; ++i) e += field_elems(t->fluid_mask[i]);
+    return e;
+}
+
 // elements of one lattice of the given storage
 uint64_t lattice_elems(const lbm_tiles *t, int storage) {
     if (!runs_layout(storage)) return (uint64_t)t->n_tiles * Q * TILE;
@@ -189,11 +196,12 @@ extern "C" int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *para
     out->state_bytes = lattice_elems(tiles, params->storage) * storage_size(params->storage);
     out->table_bytes = TableLayout((int64_t)n).total;
     out->scratch_bytes = (n + 1) * NSUM * sizeof(double);
-    out->force_bytes = n * 3 * TILE * arith_size(params->storage);
+    const size_t fe = field_entries(tiles);
+    out->force_bytes = fe * arith_size(params->storage);
     // the adjoint lattice has the layout and element type of the state (runs);
     // FP16 storage has no adjoint
     out->adjoint_bytes = params->storage == LBM_F16S ? 0 : out->state_bytes;
-    out->grad_force_bytes = n * 3 * TILE * sizeof(double);
+    out->grad_force_bytes = fe * sizeof(double);
     out->bc_bytes = n * 9 * sizeof(uint64_t);
     out->dense_nodes = (size_t)tiles->nx * (size_t)tiles->ny * (size_t)tiles->nz;
     return LBM_OK;
@@ -269,7 +277,8 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
         uint32_t *nbb32 = reinterpret_cast<uint32_t *>(host.data() + lay.nbb32_off);
         uint64_t *nbb64 = reinterpret_cast<uint64_t *>(host.data() + lay.nbb64_off);
         int32_t *xyz = reinterpret_cast<int32_t *>(host.data() + lay.xyz_off);
-        uint64_t next = 0;
+        uint64_t *fbase = reinterpret_cast<uint64_t *>(host.data() + lay.fld_off);
+        uint64_t next = 0, next_field = 0;
         for (int64_t d = 0; d < n; ++d) {
             const int64_t i = perm[d];
             rec[d].mask = tiles->fluid_mask[i];
@@ -279,6 +288,8 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
             } else {
                 rec[d].base = (uint64_t)d * Q * TILE;
             }
+            fbase[d] = next_field;
+            next_field += field_elems(tiles->fluid_mask[i]);
             for (int a = 0; a < 3; ++a) xyz[4 * d + a] = tiles->tile_xyz[3 * i + a];
             for (int a = 0; a < 3; ++a) c->corner[3 * d + a] = tiles->tile_xyz[3 * i + a];
             xyz[4 * d + 3] = 0;
@@ -313,6 +324,7 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
     c->L.tb.nbb32 = reinterpret_cast<const uint32_t *>(tb + lay.nbb32_off);
     c->L.tb.nbb64 = reinterpret_cast<const uint64_t *>(tb + lay.nbb64_off);
     c->L.tb.xyz = reinterpret_cast<const int32_t *>(tb + lay.xyz_off);
+    c->L.tb.fbase = reinterpret_cast<const uint64_t *>(tb + lay.fld_off);
     // every byte offset into a lattice (an adjoint lattice has the layout and
     // size of the state) must fit 32 bits for the 32-bit kernels
     c->L.off32 = c->state_bytes <= (size_t)UINT32_MAX && !c->params.wide_offsets;
@@ -626,6 +638,16 @@ extern "C" int lbm_tiles_to_dense(lbm_ctx *c, const void *tile_buf, int32_t ncom
     hipError_t e = launch_fill(c->stream, dense_dev, (size_t)ncomp * N);
     if (e == hipSuccess) e = launch_tiles_to_dense(c->L, tile_buf, ncomp, dtype, dense_dev, c->nx, c->ny, c->nz);
     return launched(e, "lbm_tiles_to_dense");
+}
+
+extern "C" int lbm_field_to_dense(lbm_ctx *c, const void *field_buf, int32_t dtype, double *dense_dev) {
+    CHECK_CTX(c);
+    if (!dense_dev || (!field_buf && c->n_tiles > 0)) return fail(LBM_E_INVAL, "lbm_field_to_dense: NULL buffer");
+    if (dtype != 0 && dtype != 1) return fail(LBM_E_INVAL, "lbm_field_to_dense: dtype must be 0 (f64) or 1 (f32)");
+    const size_t N = (size_t)c->nx * c->ny * c->nz;
+    hipError_t e = launch_fill(c->stream, dense_dev, 3 * N);
+    if (e == hipSuccess) e = launch_field_to_dense(c->L, field_buf, dtype, dense_dev, c->nx, c->ny, c->nz);
+    return launched(e, "lbm_field_to_dense");
 }
 
 static int adjoint_supported(lbm_ctx *c) {

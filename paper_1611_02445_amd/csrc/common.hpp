@@ -106,6 +106,15 @@ constexpr int TILE = 64;
 //         a block is exactly one 128-byte line
 // ---------------------------------------------------------------------------
 inline size_t storage_size(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
+// Per-node fields with three components (the force density and its
+// gradient) are kept per fluid slot as well: tile t owns 3*k entries at
+// fbase[t] + c*k + slot (c = x, y, z), padded to a multiple of FIELD_PAD
+// entries (128 bytes of FP64, 64 of FP32).
+constexpr uint64_t FIELD_PAD = 16;
+inline uint64_t field_elems(uint64_t mask) {
+    const uint64_t k = (uint64_t)__builtin_popcountll(mask);
+    return (3 * k + FIELD_PAD - 1) / FIELD_PAD * FIELD_PAD;
+}
 inline bool runs_layout(int storage) { return storage != LBM_F16S; }
 inline uint64_t run_elems(uint64_t mask, int storage) {
     const uint64_t L = 128 / storage_size(storage);
@@ -122,6 +131,7 @@ inline uint64_t run_elems(uint64_t mask, int storage) {
 //   [nbb32_off]  uint32 [n_tiles][20]: element offsets of the same 19 tiles
 //   [nbb64_off]  uint64 [n_tiles][20]: the same offsets in 64 bits
 //   [xyz_off]    int32  [n_tiles][4]: corner x, y, z, 0
+//   [fld_off]    uint64 [n_tiles]: entry offset of the tile's per-node field run
 // The neighbourhood is gathered once on the host, so a wave reads it with a
 // few wide scalar loads instead of chasing 19 tile numbers.
 // ---------------------------------------------------------------------------
@@ -147,7 +157,7 @@ constexpr int nb_slot(int k) {
 }
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct TableLayout {
-    size_t rec_off, nbm_off, nbb32_off, nbb64_off, xyz_off, total;
+    size_t rec_off, nbm_off, nbb32_off, nbb64_off, xyz_off, fld_off, total;
     explicit TableLayout(int64_t n_tiles) {
         const size_t n = (size_t)n_tiles;
         rec_off = 0;
@@ -155,7 +165,8 @@ struct TableLayout {
         nbb32_off = align_up(nbm_off + n * NB_STRIDE * 8, 256);
         nbb64_off = align_up(nbb32_off + n * NB_STRIDE * 4, 256);
         xyz_off = align_up(nbb64_off + n * NB_STRIDE * 8, 256);
-        total = align_up(xyz_off + n * 16, 256);
+        fld_off = align_up(xyz_off + n * 16, 256);
+        total = align_up(fld_off + n * 8, 256);
     }
 };
 
@@ -165,6 +176,7 @@ struct DevTables {
     const uint32_t *nbb32;
     const uint64_t *nbb64;
     const int32_t *xyz;
+    const uint64_t *fbase;
 };
 
 // reduction scratch: per-tile partials of 8 doubles + the final 8

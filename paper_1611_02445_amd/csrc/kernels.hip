@@ -47,6 +47,7 @@ template <> struct Codec<LBM_F64> {
     using S = double;
     using T = double;
     static constexpr bool RUNS = true;
+    static constexpr bool SCALED = false;
     static __device__ __forceinline__ T dec(S v, float) { return v; }
     static __device__ __forceinline__ S enc(T v, float) { return v; }
 };
@@ -54,6 +55,7 @@ template <> struct Codec<LBM_F32> {
     using S = float;
     using T = float;
     static constexpr bool RUNS = true;
+    static constexpr bool SCALED = false;
     static __device__ __forceinline__ T dec(S v, float) { return v; }
     static __device__ __forceinline__ S enc(T v, float) { return v; }
 };
@@ -61,8 +63,17 @@ template <> struct Codec<LBM_F16S> {
     using S = _Float16;
     using T = float;
     static constexpr bool RUNS = false;
+    // The step works on the stored scale: D_i = s d_i with s = 2^k, so
+    // decoding and encoding are bare conversions (38 fewer vector
+    // multiplications per tile).  Scaling by a power of two is exact and
+    // commutes with rounding, so this is the unscaled arithmetic up to the
+    // compiler's choice of fused multiply-adds, which differs between the two
+    // forms (stored values move by about one FP16 ulp).
+    static constexpr bool SCALED = true;
     static __device__ __forceinline__ T dec(S v, float inv_scale) { return (float)v * inv_scale; }
     static __device__ __forceinline__ S enc(T v, float scale) { return (_Float16)(v * scale); }
+    static __device__ __forceinline__ T dec_scaled(S v) { return (float)v; }
+    static __device__ __forceinline__ S enc_scaled(T v) { return (_Float16)v; }
     // Stochastic rounding to FP16 with gfx950's conversion instruction: it
     // rounds away from zero with probability equal to the discarded fraction
     // of an FP16 ulp (normal and subnormal results alike), drawing on the high
@@ -72,8 +83,8 @@ template <> struct Codec<LBM_F16S> {
     // The instruction writes one half of a 32-bit register and keeps the
     // other; `pair` carries that register from one call to the next.
     typedef _Float16 Pair __attribute__((ext_vector_type(2)));
-    static __device__ __forceinline__ S enc_sr(T v, float scale, uint32_t r, Pair &pair) {
-        pair = __builtin_amdgcn_cvt_sr_f16_f32(pair, v * scale, r, false);
+    static __device__ __forceinline__ S enc_sr_scaled(T v, uint32_t r, Pair &pair) {
+        pair = __builtin_amdgcn_cvt_sr_f16_f32(pair, v, r, false);
         return pair[0];
     }
 };
@@ -113,6 +124,11 @@ __device__ __forceinline__ int wave_tile(int wpb, int nb) {
 }
 
 __device__ __forceinline__ bool lane_on(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+__device__ __forceinline__ uint64_t field_elems_dev(uint64_t mask) {
+    const uint64_t k = (uint64_t)__builtin_popcountll(mask);
+    return (3 * k + FIELD_PAD - 1) / FIELD_PAD * FIELD_PAD;
+}
 
 // number of set bits of m below this lane
 __device__ __forceinline__ int mbcnt(uint64_t m) {
@@ -388,9 +404,13 @@ __device__ __forceinline__ void store_tile(char *lattice, const Self<RUNS, OffT>
         // value(i) is evaluated on every covered lane (callers keep the
         // values of solid lanes defined, and zero when they pass ZERO_SOLID)
         if (lane_on(cover)) {
+            // the tile's first block is wave-uniform, the lane's byte offset
+            // 32 bits, and the blocks follow at fixed distances
+            char *tile0 = lattice + (size_t)me.base * sizeof(S);
+            const uint32_t lane_off = (uint32_t)lane * (uint32_t)sizeof(S);
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                S *p = out + (me.base + (OffT)(i * TILE)) + lane;
+                S *p = reinterpret_cast<S *>(tile0 + (i * TILE * (int)sizeof(S) + lane_off));
                 S v = value(i);
                 if constexpr (!ZERO_SOLID) v = fl ? v : S(0);
                 if constexpr (STREAM) store_stream(p, v);
@@ -410,8 +430,13 @@ __device__ __forceinline__ void store_tile(char *lattice, const Self<RUNS, OffT>
 //   P_i = 3 c.u + 4.5 (c.u)^2 - 1.5 u.u,
 //   d*_i = d_i + omega (deq_i - d_i) + kg w_i (3 (c_i - u).F + 9 (c_i.u)(c_i.F))
 // ---------------------------------------------------------------------------
-template <typename T, int MODEL>
-__device__ __forceinline__ void collide(T (&d)[Q], T rho_base, T omega, T kg, T Fx, T Fy, T Fz) {
+// With SC the values are held on a scale s = 2^k (D = s d, sc = s, isc =
+// 1/s): the sums are brought back to unit scale for rho and u, and the
+// equilibrium and source terms are put on the scale; every product with a
+// power of two is exact.
+template <typename T, int MODEL, bool SC = false>
+__device__ __forceinline__ void collide(T (&d)[Q], T rho_base, T omega, T kg, T Fx, T Fy, T Fz, T sc = T(1),
+                                        T isc = T(1)) {
     T drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -419,6 +444,14 @@ __device__ __forceinline__ void collide(T (&d)[Q], T rho_base, T omega, T kg, T 
         if (CX[i]) jx += CX[i] > 0 ? d[i] : -d[i];
         if (CY[i]) jy += CY[i] > 0 ? d[i] : -d[i];
         if (CZ[i]) jz += CZ[i] > 0 ? d[i] : -d[i];
+    }
+    const T drho_s = drho;  // on the stored scale: feeds the equilibrium's drho term
+    if constexpr (SC) {
+        drho *= isc;
+        jx *= isc;
+        jy *= isc;
+        jz *= isc;
+        kg *= sc;
     }
     const T rho = rho_base + drho;
     T ux = jx + T(0.5) * Fx, uy = jy + T(0.5) * Fy, uz = jz + T(0.5) * Fz;
@@ -434,8 +467,9 @@ __device__ __forceinline__ void collide(T (&d)[Q], T rho_base, T omega, T kg, T 
     // omega deq_i = A_w + B_w P_i with A_w = omega w drho and B_w = omega w rho
     // (model 0) or omega w (model 1); the source is G_w (3 c_i.F - uF3 +
     // 9 (c_i.u)(c_i.F)) with G_w = kg w.  Per weight class:
-    const T bscale = MODEL == LBM_QUASI_COMPRESSIBLE ? rho : T(1);
-    const T od = omega * drho, ob = omega * bscale;
+    T bscale = MODEL == LBM_QUASI_COMPRESSIBLE ? rho : T(1);
+    if constexpr (SC) bscale *= sc;
+    const T od = omega * drho_s, ob = omega * bscale;
     {
         const T w = T(weight(0));
         d[0] = om1 * d[0] + (w * od - (w * ob) * usq) - (kg * w) * uF3;
@@ -469,8 +503,9 @@ __device__ __forceinline__ void collide(T (&d)[Q], T rho_base, T omega, T kg, T 
 // and M^-1 = M^T diag(1/|row|^2) since the rows are orthogonal.  The
 // conserved moments (rate 0) drop out: their part of r + G/2 is zero.
 // ---------------------------------------------------------------------------
-template <typename T, int INC>
-__device__ __forceinline__ void collide_mrt(T (&d)[Q], T rho_base, T omega, T Fx, T Fy, T Fz) {
+template <typename T, int INC, bool SC = false>
+__device__ __forceinline__ void collide_mrt(T (&d)[Q], T rho_base, T omega, T Fx, T Fy, T Fz, T sc = T(1),
+                                            T isc = T(1)) {
     T drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -478,6 +513,13 @@ __device__ __forceinline__ void collide_mrt(T (&d)[Q], T rho_base, T omega, T Fx
         if (CX[i]) jx += CX[i] > 0 ? d[i] : -d[i];
         if (CY[i]) jy += CY[i] > 0 ? d[i] : -d[i];
         if (CZ[i]) jz += CZ[i] > 0 ? d[i] : -d[i];
+    }
+    const T drho_s = drho;  // on the stored scale (see collide)
+    if constexpr (SC) {
+        drho *= isc;
+        jx *= isc;
+        jy *= isc;
+        jz *= isc;
     }
     const T rho = rho_base + drho;
     T ux = jx + T(0.5) * Fx, uy = jy + T(0.5) * Fy, uz = jz + T(0.5) * Fz;
@@ -489,15 +531,21 @@ __device__ __forceinline__ void collide_mrt(T (&d)[Q], T rho_base, T omega, T Fx
     }
     const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
     const T uF3 = T(3) * (ux * Fx + uy * Fy + uz * Fz);
-    const T bscale = INC ? T(1) : rho;
+    T bscale = INC ? T(1) : rho;
+    T ws = T(1);  // the source's weight factor on the stored scale
+    if constexpr (SC) {
+        bscale *= sc;
+        ws = sc;
+    }
     T v[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const T w = T(weight(i));
         const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
         const T cF = T(CX[i]) * Fx + T(CY[i]) * Fy + T(CZ[i]) * Fz;
-        const T deq = w * (drho + bscale * (T(3) * cu + T(4.5) * cu * cu - usq));
-        const T src = w * (T(3) * cF - uF3 + T(9) * cu * cF);
+        const T deq = w * (drho_s + bscale * (T(3) * cu + T(4.5) * cu * cu - usq));
+        T src = w * (T(3) * cF - uF3 + T(9) * cu * cF);
+        if constexpr (SC) src *= ws;
         v[i] = d[i] - deq + T(0.5) * src;
         d[i] += src;  // d_i + G_i; the relaxation is subtracted below
     }
@@ -596,10 +644,13 @@ __device__ __forceinline__ void open_boundary(T (&d)[Q], const Phys &P, int t, i
 }
 
 // the collision of a model: LBGK (0, 1) or multiple relaxation times (2, 3)
-template <typename T, int MODEL>
-__device__ __forceinline__ void collide_model(T (&d)[Q], T rho_base, T omega, T kg, T Fx, T Fy, T Fz) {
-    if constexpr (MODEL >= LBM_MRT_QUASI_COMPRESSIBLE) collide_mrt<T, (MODEL & 1)>(d, rho_base, omega, Fx, Fy, Fz);
-    else collide<T, MODEL>(d, rho_base, omega, kg, Fx, Fy, Fz);
+template <typename T, int MODEL, bool SC = false>
+__device__ __forceinline__ void collide_model(T (&d)[Q], T rho_base, T omega, T kg, T Fx, T Fy, T Fz, T sc = T(1),
+                                              T isc = T(1)) {
+    if constexpr (MODEL >= LBM_MRT_QUASI_COMPRESSIBLE)
+        collide_mrt<T, (MODEL & 1), SC>(d, rho_base, omega, Fx, Fy, Fz, sc, isc);
+    else
+        collide<T, MODEL, SC>(d, rho_base, omega, kg, Fx, Fy, Fz, sc, isc);
 }
 
 struct KArgs {
@@ -612,14 +663,30 @@ struct KArgs {
     Phys P;
 };
 
-// the per-node force field is kept in plain lane order [tile][3][64]
+// where a fluid node's entries of a per-node field live: component c at
+// fbase[t] + c * k + slot, slot = the node's rank among the tile's fluid nodes
+struct FieldSlot {
+    uint64_t base;  // entry offset of the tile's field run (wave-uniform)
+    int k;          // fluid nodes of the tile
+    int slot;
+    __device__ __forceinline__ FieldSlot(const DevTables &tb, int t, uint64_t mask) {
+        base = tb.fbase[t];
+        k = __builtin_popcountll(mask);
+        slot = mbcnt(mask);
+    }
+    __device__ __forceinline__ uint64_t entry(int c) const { return base + (uint64_t)(c * k + slot); }
+};
+
+// the per-node force field, one entry per fluid slot and component
 template <typename T>
-__device__ __forceinline__ void load_force(const Phys &P, int t, int lane, T &Fx, T &Fy, T &Fz) {
+__device__ __forceinline__ void load_force(const Phys &P, const DevTables &tb, int t, uint64_t mask, T &Fx, T &Fy,
+                                           T &Fz) {
     if (P.field) {
-        const T *f = reinterpret_cast<const T *>(P.field) + (size_t)t * 3 * TILE + lane;
-        Fx = f[0];
-        Fy = f[TILE];
-        Fz = f[2 * TILE];
+        const FieldSlot fs(tb, t, mask);
+        const T *f = reinterpret_cast<const T *>(P.field);
+        Fx = f[fs.entry(0)];
+        Fy = f[fs.entry(1)];
+        Fz = f[fs.entry(2)];
     } else {
         Fx = T(P.F[0]);
         Fy = T(P.F[1]);
@@ -655,12 +722,26 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
         load_nbhd(h, a.tb, t);
         S raw[Q];
         gather_all<false, RN, S, OffT>(raw, h, a.src, me, lane);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] = C::dec(raw[i], a.P.inv_scale);
         T Fx, Fy, Fz;
-        load_force<T>(a.P, t, lane, Fx, Fy, Fz);
-        if (a.P.bc) open_boundary<T, (MODEL & 1)>(d, a.P, t, lane, Fx, Fy, Fz);
-        collide_model<T, MODEL>(d, T(a.P.rho_base), T(a.P.omega), T(a.P.kg), Fx, Fy, Fz);
+        load_force<T>(a.P, a.tb, t, own, Fx, Fy, Fz);
+        if constexpr (C::SCALED) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) d[i] = C::dec_scaled(raw[i]);
+            if (a.P.bc) {  // the rebuild works at unit scale (exact round trip)
+#pragma unroll
+                for (int i = 0; i < Q; ++i) d[i] *= a.P.inv_scale;
+                open_boundary<T, (MODEL & 1)>(d, a.P, t, lane, Fx, Fy, Fz);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) d[i] *= a.P.scale;
+            }
+            collide_model<T, MODEL, true>(d, T(a.P.rho_base), T(a.P.omega), T(a.P.kg), Fx, Fy, Fz, T(a.P.scale),
+                                          T(a.P.inv_scale));
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) d[i] = C::dec(raw[i], a.P.inv_scale);
+            if (a.P.bc) open_boundary<T, (MODEL & 1)>(d, a.P, t, lane, Fx, Fy, Fz);
+            collide_model<T, MODEL>(d, T(a.P.rho_base), T(a.P.omega), T(a.P.kg), Fx, Fy, Fz);
+        }
     }
     if constexpr (ST == LBM_F16S) {
         if (a.P.f16_stochastic) {
@@ -671,12 +752,14 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
             const uint32_t seed = hash32(tile_seed + (uint32_t)lane);
             typename C::Pair pair = {};
             store_tile<S, RN, OffT, true, !RN>(a.dst, me, own, fl, lane, [&](int i) {
-                return C::enc_sr(d[i], a.P.scale, seed + (uint32_t)i * 0x9E3779B9u, pair);
+                return C::enc_sr_scaled(d[i], seed + (uint32_t)i * 0x9E3779B9u, pair);
             });
             return;
         }
+        store_tile<S, RN, OffT, true, !RN>(a.dst, me, own, fl, lane, [&](int i) { return C::enc_scaled(d[i]); });
+    } else {
+        store_tile<S, RN, OffT, true, !RN>(a.dst, me, own, fl, lane, [&](int i) { return C::enc(d[i], a.P.scale); });
     }
-    store_tile<S, RN, OffT, true, !RN>(a.dst, me, own, fl, lane, [&](int i) { return C::enc(d[i], a.P.scale); });
 }
 
 // the paper's measurement kernels (Section 4.1): kind 1 "read/write only",
@@ -855,8 +938,8 @@ __global__ __launch_bounds__(512) void k_macro(KArgs a, double *rho_out, double 
             jz += CZ[i] * v;
         }
     }
-    T Fx, Fy, Fz;
-    load_force<T>(a.P, t, lane, Fx, Fy, Fz);
+    T Fx = T(0), Fy = T(0), Fz = T(0);
+    if (fl) load_force<T>(a.P, a.tb, t, rec.mask, Fx, Fy, Fz);
     const double rho = a.P.rho_base + drho;
     const double mx = jx - 0.5 * (double)Fx, my = jy - 0.5 * (double)Fy, mz = jz - 0.5 * (double)Fz;
     double ux = mx, uy = my, uz = mz;
@@ -972,17 +1055,38 @@ __global__ __launch_bounds__(512) void k_set_state(KArgs a, const double *dense,
     }
 }
 
+// dense [3][nz][ny][nx] body acceleration -> force density F = rho0 g per
+// fluid slot; the pad entries after a tile's 3k are set to 0
 template <typename T>
 __global__ __launch_bounds__(512) void k_force_to_tiles(KArgs a, const double *g, T *out, int nx, int ny, int nz) {
     const int t = wave_tile(a.wpb, a.nblocks);
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
-    const bool fl = (a.tb.rec[t].mask >> lane) & 1;
+    const uint64_t mask = a.tb.rec[t].mask;
+    const FieldSlot fs(a.tb, t, mask);
+    if ((mask >> lane) & 1) {
+        const size_t N = (size_t)nx * ny * nz;
+        const size_t n = dense_index(a.tb.xyz + 4 * (size_t)t, lane, nx, ny);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[fs.entry(c)] = (T)(a.P.rho0 * g[(size_t)c * N + n]);
+    }
+    const int used = 3 * fs.k;
+    if (lane < (int)field_elems_dev(mask) - used) out[fs.base + (uint64_t)(used + lane)] = T(0);
+}
+
+// per-fluid-slot field [3 components] -> dense FP64 [3][nz][ny][nx]
+template <typename T>
+__global__ __launch_bounds__(512) void k_field_to_dense(KArgs a, const T *in, double *dense, int nx, int ny, int nz) {
+    const int t = wave_tile(a.wpb, a.nblocks);
+    if (t >= a.n_tiles) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t mask = a.tb.rec[t].mask;
+    if (!((mask >> lane) & 1)) return;  // the dense array was zero-filled
+    const FieldSlot fs(a.tb, t, mask);
     const size_t N = (size_t)nx * ny * nz;
     const size_t n = dense_index(a.tb.xyz + 4 * (size_t)t, lane, nx, ny);
-    T *o = out + (size_t)t * 3 * TILE + lane;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) o[c * TILE] = fl ? (T)(a.P.rho0 * g[(size_t)c * N + n]) : T(0);
+    for (int c = 0; c < 3; ++c) dense[(size_t)c * N + n] = (double)in[fs.entry(c)];
 }
 
 template <typename T>
@@ -1170,7 +1274,7 @@ struct AdjArgs {
     const char *s;      // forward lattice feeding the forward gather
     const char *eta_in; // adjoint lattice feeding the reverse gather
     char *out;          // adjoint lattice written
-    double *grad;       // [n_tiles][3][64] FP64 (lane order), dL/dg
+    double *grad;       // dL/dg, FP64 per fluid slot (the force field's layout)
     DevTables tb;
     int n_tiles;
     int wpb;
@@ -1201,7 +1305,7 @@ __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
         T g[Q];
         gather_all<false, true, T, OffT>(g, h, a.s, me, lane);
         T Fx, Fy, Fz;
-        load_force<T>(a.P, t, lane, Fx, Fy, Fz);
+        load_force<T>(a.P, a.tb, t, own, Fx, Fy, Fz);
         T lam[Q];
         T irT = T(1);
         if constexpr (INC) {
@@ -1227,10 +1331,14 @@ __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
         gx += T(-0.5) * irT * inv_n;
     }
     store_tile<T, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
-    double *go = a.grad + (size_t)t * 3 * TILE + lane;
-    go[0] = fl ? a.P.rho0 * (double)gx : 0.0;
-    go[TILE] = fl ? a.P.rho0 * (double)gy : 0.0;
-    go[2 * TILE] = fl ? a.P.rho0 * (double)gz : 0.0;
+    const FieldSlot fs(a.tb, t, own);
+    if (fl) {
+        a.grad[fs.entry(0)] = a.P.rho0 * (double)gx;
+        a.grad[fs.entry(1)] = a.P.rho0 * (double)gy;
+        a.grad[fs.entry(2)] = a.P.rho0 * (double)gz;
+    }
+    const int used = 3 * fs.k;  // the seed also clears the run's pad entries
+    if (lane < (int)field_elems_dev(own) - used) a.grad[fs.base + (uint64_t)(used + lane)] = 0.0;
 }
 
 // step: lam_{t-1} = S^T eta_t (reverse gather), g_{t-1} = S s_{t-2},
@@ -1264,13 +1372,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(AdjWaves<ST
         T lam[Q], g[Q];
         gather_pairs<true, T, OffT>(lam, g, h, a.eta_in, a.s, me, lane);
         T Fx, Fy, Fz;
-        load_force<T>(a.P, t, lane, Fx, Fy, Fz);
+        load_force<T>(a.P, a.tb, t, own, Fx, Fy, Fz);
         T gx, gy, gz;
         collide_jt_model<T, MODEL>(g, T(a.P.rho_base), lam, T(a.P.omega), T(a.P.kg), Fx, Fy, Fz, eta, gx, gy, gz);
-        double *go = a.grad + (size_t)t * 3 * TILE + lane;
-        go[0] += a.P.rho0 * (double)gx;
-        go[TILE] += a.P.rho0 * (double)gy;
-        go[2 * TILE] += a.P.rho0 * (double)gz;
+        const FieldSlot fs(a.tb, t, own);
+        a.grad[fs.entry(0)] += a.P.rho0 * (double)gx;
+        a.grad[fs.entry(1)] += a.P.rho0 * (double)gy;
+        a.grad[fs.entry(2)] += a.P.rho0 * (double)gz;
     }
     store_tile<T, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
 }
@@ -1516,6 +1624,20 @@ hipError_t launch_force_to_tiles(const Launch &L, const Phys &P, const double *g
     else
         hipLaunchKernelGGL(k_force_to_tiles<float>, dim3(L.grid), block_of(L), 0, L.stream, a, g,
                            reinterpret_cast<float *>(tile_buf), nx, ny, nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_to_dense(const Launch &L, const void *field, int dtype, double *dense, int nx, int ny,
+                                 int nz) {
+    if (L.n_tiles == 0) return hipSuccess;
+    Phys P{};
+    const KArgs a = make_args(L, P, nullptr, nullptr);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_field_to_dense<double>, dim3(L.grid), block_of(L), 0, L.stream, a,
+                           reinterpret_cast<const double *>(field), dense, nx, ny, nz);
+    else
+        hipLaunchKernelGGL(k_field_to_dense<float>, dim3(L.grid), block_of(L), 0, L.stream, a,
+                           reinterpret_cast<const float *>(field), dense, nx, ny, nz);
     return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@ struct Phys {
     double rho0;       // reference density (force density F = rho0 g)
     double rho_base;   // shift of the stored values: 0 for FP64, rho0 for reduced storage
     double F[3];       // uniform force density (used when field == nullptr)
-    const void *field; // tile-order force density [n_tiles][3][64] of the arithmetic type, or null
+    const void *field; // per-node force density of the arithmetic type (per fluid slot), or null
     float scale;       // FP16: 2^k; 1 otherwise
     float inv_scale;
     double inv_nfluid; // 1 / N_fluid (adjoint loss normalisation)
@@ -47,6 +47,8 @@ hipError_t launch_get_state(const Launch &L, const Phys &P, const void *state, d
 hipError_t launch_set_state(const Launch &L, const Phys &P, const double *dense, void *state, int nx, int ny, int nz);
 hipError_t launch_force_to_tiles(const Launch &L, const Phys &P, const double *g_dense, void *tile_buf, int nx,
                                  int ny, int nz);
+hipError_t launch_field_to_dense(const Launch &L, const void *field, int dtype, double *dense, int nx, int ny,
+                                 int nz);
 hipError_t launch_tiles_to_dense(const Launch &L, const void *tile_buf, int ncomp, int dtype, double *dense, int nx,
                                  int ny, int nz);
 hipError_t launch_adjoint_seed(const Launch &L, const Phys &P, const void *s_prev, void *eta, double *grad);

@@ -238,6 +238,14 @@ class Lattice:
         call("lbm_set_state", self.ctx, _vp(f), _vp(state))
         self.stream.synchronize()
 
+    def field_to_dense(self, field_buf, dtype=0):
+        """A per-node field (force density, force gradient) as a dense FP64
+        [3, nz, ny, nx] tensor."""
+        torch = self.torch
+        out = torch.empty((3,) + self.dense_shape, dtype=torch.float64, device=self.device)
+        call("lbm_field_to_dense", self.ctx, _vp(field_buf), int(dtype), _vp(out))
+        return out
+
     def tiles_to_dense(self, tile_buf, ncomp, dtype=0):
         torch = self.torch
         out = torch.empty((ncomp,) + self.dense_shape, dtype=torch.float64, device=self.device)

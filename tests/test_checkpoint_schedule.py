@@ -75,7 +75,7 @@ class FakeLattice:
     def adjoint_get(self, buf):
         return buf.t
 
-    def tiles_to_dense(self, buf, n, dtype):
+    def field_to_dense(self, buf, dtype=0):
         return None
 
 
