@@ -133,3 +133,27 @@ def test_stream_probe_rejects_overlap_and_misalignment():
     assert L.lbm_stream_probe(None, 3, ctypes.c_void_p(base + 8), ctypes.c_void_p(1 << 30), 1024, 8, 64) == -1
     assert b"aligned" in L.lbm_last_error()
     assert L.lbm_stream_probe(None, 1, None, ctypes.c_void_p(1 << 30), 1024, 8, 64) == -1
+
+
+def test_field_to_dense_validation():
+    L = _abi.lib()
+    assert L.lbm_field_to_dense(None, None, 0, None) == -1
+
+
+def test_field_and_lattice_sizes_follow_the_fluid_slots():
+    """Partly solid tiles: a lattice holds 19 k values per tile and a per-node
+    field 3 k entries, each padded (128-byte lines; 16 entries)."""
+    rng = np.random.default_rng(81)
+    solid = (rng.random((12, 16, 20)) < 0.6).astype(np.uint8)
+    t = Tiling(solid, 7)
+    k = np.array([bin(int(m)).count("1") for m in t.arrays()["fluid_mask"]])
+    for storage, nd, na in ((0, 8, 8), (1, 4, 4), (2, 2, 4)):
+        sz = _abi.Sizes()
+        _abi.call("lbm_required_bytes", t._ptr, ctypes.byref(_params(storage=storage)), ctypes.byref(sz))
+        fe = int(((3 * k + 15) // 16 * 16).sum())
+        assert sz.force_bytes == fe * na and sz.grad_force_bytes == fe * 8
+        if storage != 2:
+            L = 128 // nd
+            assert sz.state_bytes == int(((19 * k + L - 1) // L * L).sum()) * nd
+        else:  # FP16 keeps whole 64-slot blocks per kept tile
+            assert sz.state_bytes == t.n_tiles * 19 * 64 * 2
