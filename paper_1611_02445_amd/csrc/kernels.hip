@@ -27,6 +27,7 @@
 // halfway bounce-back value at the node itself.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "kernels.hpp"
@@ -289,6 +290,55 @@ __device__ __forceinline__ OffT source_elem(const Nbhd<OffT> &h, int lane) {
     return e;
 }
 
+// Plain layout with 32-bit offsets: the element of lane n is n + C_r for the
+// region r holding n, C_r = base_K + I * 64 + OFF (wave-uniform).  A lane
+// select per region costs a move of C_r into a vector register and the
+// select (an instruction reads one scalar operand, and the lane mask is
+// one); instead the element is n + C_00 plus, for each axis a the shift
+// crosses, (M_a AND (C_a - C_00)), where M_a is all ones on the lanes that
+// leave the tile along a, and for the two axes of an edge direction the
+// inclusion-exclusion term (M_a AND M_b AND (C_ab - C_a - C_b + C_00)).
+// Unsigned wrap-around keeps every partial sum exact modulo 2^32.
+template <int SX, int SY, int SZ, int BX, int BY, int BZ, int I>
+__device__ __forceinline__ uint32_t plain_region_const(const Nbhd<uint32_t> &h) {
+    using R = Region<SX, SY, SZ, BX, BY, BZ>;
+    static_assert(R::EXISTS, "every region of a face or edge shift holds lanes");
+    return h.base[R::K] + (uint32_t)(I * TILE + R::OFF);
+}
+
+// all ones on the lanes whose node plus the unit shift (AX, AY, AZ) leaves
+// the tile
+template <int AX, int AY, int AZ>
+__device__ __forceinline__ uint32_t axis_lanes() {
+    constexpr uint64_t M = region_mask(AX, AY, AZ, AX != 0, AY != 0, AZ != 0);
+    return lane_on(M) ? 0xffffffffu : 0u;
+}
+
+template <int SX, int SY, int SZ, int I>
+__device__ __forceinline__ uint32_t plain_source_elem(const Nbhd<uint32_t> &h, int lane) {
+    // the first and (for an edge direction) the second axis the shift moves along
+    constexpr int A1X = SX, A1Y = SX ? 0 : SY, A1Z = (SX || SY) ? 0 : SZ;
+    constexpr int A2X = 0, A2Y = SX ? SY : 0, A2Z = (SX || SY) ? SZ : 0;
+    constexpr bool EDGE = (A2Y != 0) || (A2Z != 0);
+    const uint32_t c00 = plain_region_const<SX, SY, SZ, 0, 0, 0, I>(h);
+    const uint32_t c1 = plain_region_const<SX, SY, SZ, A1X != 0, A1Y != 0, A1Z != 0, I>(h);
+    const uint32_t m1 = axis_lanes<A1X, A1Y, A1Z>();
+    uint32_t e = (uint32_t)lane + c00 + (m1 & (c1 - c00));
+    if constexpr (EDGE) {
+        const uint32_t c2 = plain_region_const<SX, SY, SZ, 0, A2Y != 0, A2Z != 0, I>(h);
+        const uint32_t c12 = plain_region_const<SX, SY, SZ, A1X != 0, (A1Y != 0) || (A2Y != 0), A2Z != 0, I>(h);
+        const uint32_t m2 = axis_lanes<A2X, A2Y, A2Z>();
+        e += (m2 & (c2 - c00)) + ((m1 & m2) & (c12 - c1 - c2 + c00));
+    }
+    return e;
+}
+
+template <int SX, int SY, int SZ, int I, bool RUNS, typename OffT>
+__device__ __forceinline__ OffT gather_source_elem(const Nbhd<OffT> &h, int lane) {
+    if constexpr (!RUNS && std::is_same<OffT, uint32_t>::value) return plain_source_elem<SX, SY, SZ, I>(h, lane);
+    else return source_elem<SX, SY, SZ, I, RUNS, OffT>(h, lane);
+}
+
 template <int I, bool REV, bool RUNS, typename S, typename OffT>
 __device__ __forceinline__ S gather_one(const Nbhd<OffT> &h, const char *base, const Self<RUNS, OffT> &me, int lane) {
     if constexpr (I == 0) {
@@ -299,7 +349,7 @@ __device__ __forceinline__ S gather_one(const Nbhd<OffT> &h, const char *base, c
         constexpr int SZ = REV ? CZ[I] : -CZ[I];
         constexpr int OP = opposite(I);
         const uint64_t ok_mask = source_fluid<SX, SY, SZ>(h);
-        const OffT e = source_elem<SX, SY, SZ, I, RUNS, OffT>(h, lane);
+        const OffT e = gather_source_elem<SX, SY, SZ, I, RUNS, OffT>(h, lane);
         return load_elem<OffT, S>(base, lane_on(ok_mask) ? e : me.elem(OP));
     }
 }
