@@ -177,7 +177,9 @@ def time_adjoint(args, torch):
            "MFLUPS_adjoint_kernels": round(nf * T / (kern_ms / 1e3) / 1e6, 1),
            "MFLUPS_backward_incl_recompute": round(nf * T / (total_ms / 1e3) / 1e6, 1),
            "recompute_steps": run.recompute_steps,
-           "bytes_per_fluid_update_adjoint": 3 * 19 * 8 + 48}
+           # two gathered lattices and one written, the force density read,
+           # the FP64 gradient read and written
+           "bytes_per_fluid_update_adjoint": 3 * 19 * 8 + 3 * 8 + 2 * 3 * 8}
     ms = kern_ms / T
     out["adjoint_hbm_frac"] = round(out["bytes_per_fluid_update_adjoint"] * nf / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     log(f"[bench] adjoint: {out['MFLUPS_adjoint_kernels']} MFLUPS kernels, "
@@ -206,6 +208,41 @@ def time_adjoint(args, torch):
         del lm, e_in, e_out, grad
     out["MFLUPS_adjoint_step_other_models"] = other
     log(f"[bench] adjoint step, other models: {other}")
+    return out
+
+
+def time_vessel(args, torch, steps=500):
+    """The 512^3 synthetic vessel network (binary tree of capsules, about 5%
+    fluid, mirrored into loops through periodic x; tau 0.6, g_x 1e-5): step
+    MFLUPS of FP64, FP32 and FP16-shifted storage on the sparsest geometry."""
+    from paper_1611_02445_amd import inputs
+    from paper_1611_02445_amd.lattice import Lattice
+    t0 = time.time()
+    solid, L0 = inputs.vessel_tree(n=512)
+    out = {"workload": "512^3 vessel network, radius 24 x 0.8 per level, 8 levels, ~5% fluid; tau 0.6, g_x 1e-5",
+           "fluid_fraction": round(float((solid == 0).mean()), 5), "steps": steps}
+    log(f"[bench] vessel 512^3: fluid {out['fluid_fraction']:.4f} ({time.time() - t0:.1f}s)")
+    for st in ("f64", "f32", "f16s"):
+        lat = Lattice(solid, 0.6, periodic=7, storage=st, tiles_per_wg=args.tpw, tile_order=args.order,
+                      check_u_max=True)
+        lat.init()
+        lat.set_force((1e-5, 0.0, 0.0))
+        lat.step(20)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(lat.stream)
+        lat.step(steps)
+        ev1.record(lat.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        out.update(tiles=lat.n_tiles, tile_grid=lat.tiling.tx * lat.tiling.ty * lat.tiling.tz,
+                   fluid_nodes=lat.n_fluid, eta_t=round(lat.tiling.eta_t, 4))
+        out[st] = {"MFLUPS": round(lat.n_fluid / (ms / 1e3) / 1e6, 1), "us_per_step": round(ms * 1e3, 2),
+                   "hbm_frac": round(BYTES_PER_UPDATE[st] * lat.n_fluid / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"[bench] vessel {st}: {out[st]['MFLUPS']} MFLUPS")
+        lat.macroscopic(fields=False)  # u_max check
+        del lat
+        torch.cuda.empty_cache()
     return out
 
 
@@ -264,7 +301,8 @@ def time_pack1024(args, torch):
            "memory_GB": round(run.memory_bytes() / 1e9, 1), "recompute_steps": run.recompute_steps,
            "MFLUPS_adjoint_kernels": round(nf * T / (kern_ms / 1e3) / 1e6, 1),
            "MFLUPS_backward_incl_recompute": round(nf * T / (back_ms / 1e3) / 1e6, 1),
-           "bytes_per_fluid_update_adjoint": 3 * 19 * 4 + 48,
+           # uniform force here: no force field to read
+           "bytes_per_fluid_update_adjoint": 3 * 19 * 4 + 2 * 3 * 8,
            "loss": L}
     out["adjoint_hbm_frac"] = round(out["bytes_per_fluid_update_adjoint"] * nf / (kern_ms / T / 1e3) / 1e9
                                     / HBM_PEAK_GBS, 4)
@@ -700,6 +738,8 @@ def main():
     ap.add_argument("--adj-k", type=int, default=100, help="adjoint checkpoint interval K")
     ap.add_argument("--pack1024", action="store_true",
                     help="also run the 1024x512x512 FP32 forward + adjoint workload (about 2 minutes)")
+    ap.add_argument("--vessel", action="store_true",
+                    help="also time the step on the 512^3 vessel network (about 5% fluid)")
     ap.add_argument("--sweep192", action="store_true",
                     help="also time the step on 192^3 random sphere arrays at porosities 0.9..0.1")
     ap.add_argument("--sweep-cavity", action="store_true",
@@ -869,6 +909,9 @@ def main():
         torch.cuda.empty_cache()
     if args.pack1024:
         result["pack1024"] = time_pack1024(args, torch)
+        torch.cuda.empty_cache()
+    if args.vessel:
+        result["vessel512"] = time_vessel(args, torch)
         torch.cuda.empty_cache()
     if args.sweep192:
         result["sphere_arrays_192"] = sweep_sphere_arrays(args, torch)
