@@ -1380,7 +1380,7 @@ __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
         collide_jt_model<T, MODEL>(g, rb, lam, om, kg, Fx, Fy, Fz, eta, gx, gy, gz);
         gx += T(-0.5) * irT * inv_n;
     }
-    store_tile<T, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
+    store_tile<T, true, OffT, true>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
     const FieldSlot fs(a.tb, t, own);
     if (fl) {
         a.grad[fs.entry(0)] = a.P.rho0 * (double)gx;
@@ -1393,6 +1393,10 @@ __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
 
 // step: lam_{t-1} = S^T eta_t (reverse gather), g_{t-1} = S s_{t-2},
 // eta_{t-1} = J^T lam_{t-1}, grad += rho0 (dC/dF)^T lam_{t-1}
+// The adjoint lattice is written with non-temporal stores, as the forward
+// step writes its lattice: the written lines then do not displace the lines
+// of the two gathered lattices that neighbouring tiles read again from L2
+// (FP64 LBGK step on the 128^3 pack 124.7 -> 118.5 us, LBMRT 137.1 -> 132.1).
 // Waves per SIMD the adjoint step asks the register allocator for.  The
 // FP32 quasi-compressible LBMRT step with 32-bit offsets needs 131 VGPRs
 // unconstrained (3 waves); at 4 it fits 128 with no spill and runs 6%
@@ -1430,7 +1434,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(AdjWaves<ST
         a.grad[fs.entry(1)] += a.P.rho0 * (double)gy;
         a.grad[fs.entry(2)] += a.P.rho0 * (double)gz;
     }
-    store_tile<T, true, OffT, false>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
+    store_tile<T, true, OffT, true>(a.out, me, own, fl, lane, [&](int i) { return eta[i]; });
 }
 
 // final: lam_0 = S^T eta_1
