@@ -93,6 +93,25 @@ constexpr double mrt_rate(int k) {
     }
 }
 
+// Opposite directions pair up (9 pairs, the lower index first); every moment
+// row is either even or odd under c -> -c (the scalar and tensor moments even,
+// the vector ones odd)
+constexpr int pair_first(int p) {
+    int n = 0;
+    for (int i = 1; i < Q; ++i) {
+        if (opposite(i) < i) continue;
+        if (n == p) return i;
+        ++n;
+    }
+    return -1;
+}
+constexpr int NPAIR = 9;
+constexpr bool mrt_row_odd(int k) {
+    for (int i = 1; i < Q; ++i)
+        if (mrt_coef(k, i) != -mrt_coef(k, opposite(i))) return false;
+    return true;
+}
+
 // lane n = x + 4y + 16z inside a tile (the XYZ map of Eq. 11)
 constexpr int TILE = 64;
 

@@ -545,6 +545,73 @@ __device__ __forceinline__ void collide(T (&d)[Q], T rho_base, T omega, T kg, T 
 }
 
 // ---------------------------------------------------------------------------
+// out = R v for the multiple-relaxation-time operator
+// R = M^T diag(s_k / |row k|^2) M (the rows of M are orthogonal).  Each row is
+// even or odd under c -> -c, so it reads either the rest value and the 9 sums
+// v_i + v_opp(i) or the 9 differences v_i - v_opp(i), and the outputs of a
+// pair share one even and one odd sum: out_i = E + O, out_opp(i) = E - O.
+// About half the operations of the plain product (both triangular halves of
+// the integer matrix are folded by the compiler either way).
+// ---------------------------------------------------------------------------
+// Every index below is a template argument, so no loop is left for the
+// compiler to unroll (a loop it kept would index the value arrays at run
+// time and move them to scratch memory); sums start from -0, the identity of
+// addition, so the first term needs no add.
+template <int K, int P, typename T>
+__device__ __forceinline__ void mrt_row_term(T &acc, const T (&vs)[NPAIR], const T (&va)[NPAIR]) {
+    constexpr int c = MRT.c[K][pair_first(P)];
+    if constexpr (c != 0) acc += T(c) * (mrt_row_odd(K) ? va[P] : vs[P]);
+}
+template <int K, typename T, int... Ps>
+__device__ __forceinline__ T mrt_moment(T omega, T v0, const T (&vs)[NPAIR], const T (&va)[NPAIR],
+                                        std::integer_sequence<int, Ps...>) {
+    if constexpr (mrt_rate(K) == 0.0) {
+        return T(0);
+    } else {
+        T acc = T(-0.0);
+        if constexpr (!mrt_row_odd(K) && MRT.c[K][0] != 0) acc += T(MRT.c[K][0]) * v0;
+        (mrt_row_term<K, Ps, T>(acc, vs, va), ...);
+        const T rate = mrt_rate(K) < 0.0 ? omega : T(mrt_rate(K));
+        return acc * (rate * T(1.0 / MRT.n[K]));
+    }
+}
+// the even (ODD = false) or odd part of column I of M^T applied to mu
+template <int I, bool ODD, int K, typename T>
+__device__ __forceinline__ void mrt_col_term(T &acc, const T (&mu)[Q]) {
+    constexpr int c = MRT.c[K][I];
+    if constexpr (mrt_rate(K) != 0.0 && c != 0 && mrt_row_odd(K) == ODD) acc += T(c) * mu[K];
+}
+template <int I, bool ODD, typename T, int... Ks>
+__device__ __forceinline__ T mrt_column(const T (&mu)[Q], std::integer_sequence<int, Ks...>) {
+    T acc = T(-0.0);
+    (mrt_col_term<I, ODD, Ks, T>(acc, mu), ...);
+    return acc;
+}
+template <int P, typename T>
+__device__ __forceinline__ void mrt_pair_out(const T (&mu)[Q], T (&out)[Q]) {
+    constexpr int i = pair_first(P), j = opposite(pair_first(P));
+    const T E = mrt_column<i, false, T>(mu, std::make_integer_sequence<int, Q>{});
+    const T O = mrt_column<i, true, T>(mu, std::make_integer_sequence<int, Q>{});
+    out[i] = E + O;
+    out[j] = E - O;
+}
+template <typename T, int... Ps, int... Ks>
+__device__ __forceinline__ void mrt_relax_impl(const T (&v)[Q], T omega, T (&out)[Q], std::integer_sequence<int, Ps...>,
+                                               std::integer_sequence<int, Ks...>) {
+    T vs[NPAIR], va[NPAIR];
+    ((vs[Ps] = v[pair_first(Ps)] + v[opposite(pair_first(Ps))], va[Ps] = v[pair_first(Ps)] - v[opposite(pair_first(Ps))]),
+     ...);
+    T mu[Q];
+    ((mu[Ks] = mrt_moment<Ks, T>(omega, v[0], vs, va, std::make_integer_sequence<int, NPAIR>{})), ...);
+    out[0] = mrt_column<0, false, T>(mu, std::make_integer_sequence<int, Q>{});
+    (mrt_pair_out<Ps, T>(mu, out), ...);
+}
+template <typename T>
+__device__ __forceinline__ void mrt_relax(const T (&v)[Q], T omega, T (&out)[Q]) {
+    mrt_relax_impl<T>(v, omega, out, std::make_integer_sequence<int, NPAIR>{}, std::make_integer_sequence<int, Q>{});
+}
+
+// ---------------------------------------------------------------------------
 // multiple relaxation times (the paper's LBMRT), on shifted values: with
 // r_i = d_i - deq_i and the Guo source G_i = w_i (3 (c_i - u).F + 9 (c_i.u)(c_i.F)),
 //   m* = m - S (m - m_eq) + (I - S/2) M G,  f* = M^-1 m*
@@ -599,26 +666,10 @@ __device__ __forceinline__ void collide_mrt(T (&d)[Q], T rho_base, T omega, T Fx
         v[i] = d[i] - deq + T(0.5) * src;
         d[i] += src;  // d_i + G_i; the relaxation is subtracted below
     }
-    T mu[Q];
+    T rv[Q];
+    mrt_relax<T>(v, omega, rv);
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-        mu[k] = T(0);
-        if (mrt_rate(k) == 0.0) continue;
-        T acc = T(0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-            if (MRT.c[k][i]) acc += T(MRT.c[k][i]) * v[i];
-        const T rate = mrt_rate(k) < 0.0 ? omega : T(mrt_rate(k));
-        mu[k] = acc * (rate * T(1.0 / MRT.n[k]));
-    }
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        T acc = T(0);
-#pragma unroll
-        for (int k = 0; k < Q; ++k)
-            if (mrt_rate(k) != 0.0 && MRT.c[k][i]) acc += T(MRT.c[k][i]) * mu[k];
-        d[i] -= acc;
-    }
+    for (int i = 0; i < Q; ++i) d[i] -= rv[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1180,9 +1231,9 @@ __device__ __forceinline__ void collide_jt(const T (&d)[Q], T rho_base, const T 
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         drho += d[i];
-        jx += T(CX[i]) * d[i];
-        jy += T(CY[i]) * d[i];
-        jz += T(CZ[i]) * d[i];
+        if (CX[i]) jx += CX[i] > 0 ? d[i] : -d[i];
+        if (CY[i]) jy += CY[i] > 0 ? d[i] : -d[i];
+        if (CZ[i]) jz += CZ[i] > 0 ? d[i] : -d[i];
     }
     const T rho = rho_base + drho;
     T ir = T(1), ro = omega;
@@ -1249,9 +1300,9 @@ __device__ __forceinline__ void collide_jt_mrt(const T (&d)[Q], T rho_base, cons
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         drho += d[i];
-        jx += T(CX[i]) * d[i];
-        jy += T(CY[i]) * d[i];
-        jz += T(CZ[i]) * d[i];
+        if (CX[i]) jx += CX[i] > 0 ? d[i] : -d[i];
+        if (CY[i]) jy += CY[i] > 0 ? d[i] : -d[i];
+        if (CZ[i]) jz += CZ[i] > 0 ? d[i] : -d[i];
     }
     const T rho = rho_base + drho;
     T ir = T(1);
@@ -1259,27 +1310,14 @@ __device__ __forceinline__ void collide_jt_mrt(const T (&d)[Q], T rho_base, cons
     const T ux = (jx + T(0.5) * Fx) * ir, uy = (jy + T(0.5) * Fy) * ir, uz = (jz + T(0.5) * Fz) * ir;
     const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
     const T bs = INC ? T(1) : rho;
-    T mk[Q];
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-        mk[k] = T(0);
-        if (mrt_rate(k) == 0.0) continue;
-        T acc = T(0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-            if (MRT.c[k][i]) acc += T(MRT.c[k][i]) * lam[i];
-        const T rate = mrt_rate(k) < 0.0 ? omega : T(mrt_rate(k));
-        mk[k] = acc * (rate * T(1.0 / MRT.n[k]));
-    }
+    T rl[Q];  // R^T lam = R lam (R is symmetric)
+    mrt_relax<T>(lam, omega, rl);
     // P = sum (3a + 9a c.u + 9b c.F) c and Pd = sum (3b + 9b c.u) c with
     // a = mu w bs, b = nu w; Sa = sum a, Sb = sum b
     T A = 0, Sa = 0, Sb = 0, px = 0, py = 0, pz = 0, qx = 0, qy = 0, qz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        T mu = T(0);
-#pragma unroll
-        for (int k = 0; k < Q; ++k)
-            if (mrt_rate(k) != 0.0 && MRT.c[k][i]) mu += T(MRT.c[k][i]) * mk[k];
+        const T mu = rl[i];
         const T nu = lam[i] - T(0.5) * mu;
         const T w = T(weight(i));
         const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
@@ -1337,7 +1375,11 @@ struct AdjArgs {
 // u_x = (sum c_x s - F_x/2)/rho (quasi-compressible) lam_T depends on s_T; with
 // u_x = sum c_x s - F_x/2 (incompressible) it is c_x / N_fluid.
 template <int ST, int MODEL, typename OffT>
-__global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
+struct AdjWaves;
+
+template <int ST, int MODEL, typename OffT>
+__global__ __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(1, AdjWaves<ST, MODEL, OffT>::max))) void k_adj_seed(AdjArgs a) {
     constexpr int INC = MODEL & 1;
     using T = typename Codec<ST>::S;
     const int t = wave_tile(a.wpb, a.nblocks);
@@ -1402,14 +1444,18 @@ __global__ __launch_bounds__(512) void k_adj_seed(AdjArgs a) {
 // unconstrained (3 waves); at 4 it fits 128 with no spill and runs 6%
 // faster.  Every other instance keeps the allocator's choice: at 4 waves the
 // 64-bit-offset one spills, and the FP64 ones spill and cost 33% (LBGK) to
-// 3.4x (LBMRT).
+// 3.4x (LBMRT).  The FP64 LBMRT seed and step are held to at most 2 waves:
+// the incompressible one needs 160-186 VGPRs, and given room for a third
+// wave the allocator spilled 160 bytes per lane to reach it.
 template <int ST, int MODEL, typename OffT>
 struct AdjWaves {
     static constexpr int value = (ST == 1 && MODEL == 2 && sizeof(OffT) == 4) ? 4 : 1;
+    static constexpr int max = (ST == 0 && MODEL >= 2) ? 2 : 8;
 };
 
 template <int ST, int MODEL, typename OffT>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(AdjWaves<ST, MODEL, OffT>::value))) void k_adj_step(
+__global__ __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(AdjWaves<ST, MODEL, OffT>::value, AdjWaves<ST, MODEL, OffT>::max))) void k_adj_step(
     AdjArgs a) {
     using T = typename Codec<ST>::S;
     const int t = wave_tile(a.wpb, a.nblocks);
