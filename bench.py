@@ -128,16 +128,16 @@ def time_storage(solid, storage, args, torch, want_state=False, model="qc"):
     return out
 
 
-def time_calib(solid, args, torch, kernel=None, launches=None, lat=None):
-    """The paper's measurement kernels (Section 4.1) on the same tiles and
-    launch shape as the FP64 step: "read/write only" (rw) and "propagation
-    only" (prop)."""
+def time_calib(solid, args, torch, kernel=None, launches=None, lat=None, storage="f64"):
+    """The paper's measurement kernels (Section 4.1) on the same tiles,
+    storage and launch shape as the step: "read/write only" (rw) and
+    "propagation only" (prop)."""
     from paper_1611_02445_amd.lattice import Lattice
     kernel = kernel or args.kernel
     launches = launches or args.steps
     kind = 1 if kernel == "rw" else 2
     if lat is None:
-        lat = Lattice(solid, args.tau, periodic=7, storage="f64", tiles_per_wg=args.tpw, tile_order=args.order)
+        lat = Lattice(solid, args.tau, periodic=7, storage=storage, tiles_per_wg=args.tpw, tile_order=args.order)
         lat.init()
     a, b = lat.new_state(), lat.new_state()
     a.copy_(lat.current_state())
@@ -155,8 +155,8 @@ def time_calib(solid, args, torch, kernel=None, launches=None, lat=None):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / launches
     nf = lat.n_fluid
-    gbs = BYTES_PER_UPDATE["f64"] * nf / (ms / 1e3) / 1e9
-    log(f"[bench] {kernel}-only: {nf / (ms / 1e3) / 1e6:.1f} MFLUPS, {ms * 1e3:.1f} us, {gbs:.0f} GB/s")
+    gbs = BYTES_PER_UPDATE[storage] * nf / (ms / 1e3) / 1e9
+    log(f"[bench] {kernel}-only {storage}: {nf / (ms / 1e3) / 1e6:.1f} MFLUPS, {ms * 1e3:.1f} us, {gbs:.0f} GB/s")
     return {"kernel": kernel, "ms_per_launch": ms, "MFLUPS": nf / (ms / 1e3) / 1e6, "GBs": gbs,
             "frac": gbs / HBM_PEAK_GBS, "fluid_nodes": nf, "tiles": lat.n_tiles}
 
@@ -902,6 +902,13 @@ def main():
                         "bytes_per_fluid_update": BYTES_PER_UPDATE[st]}
         log(f"[bench] {st}: {mf:.1f} MFLUPS (x{mf / mflups:.2f})")
         del rv
+        if st in BYTES_PER_UPDATE and st != "f32u":
+            # what the same layout sustains with no collision (propagation
+            # only) and with no gather either (read/write only)
+            for kname in ("rw", "prop"):
+                c = time_calib(solid, args, torch, kernel=kname, launches=min(args.steps, 500), storage=st)
+                variants[st]["read_write_only_ms" if kname == "rw" else "propagation_only_ms"] = \
+                    round(c["ms_per_launch"], 6)
     if variants and args.error_steps > 0:
         # the stated error of each storage type: a fixed run from rest,
         # independent of --steps
