@@ -808,6 +808,14 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
     if (t >= a.n_tiles) return;
     const int lane = (int)(threadIdx.x & 63);
     const TileRec rec = a.tb.rec[t];
+    // the tile's position (keys the stochastic rounding), read with its record
+    uint32_t cx = 0, cy = 0, cz = 0;
+    if constexpr (ST == LBM_F16S) {
+        const int32_t *c = a.tb.xyz + 4 * (size_t)t;
+        cx = (uint32_t)c[0];
+        cy = (uint32_t)c[1];
+        cz = (uint32_t)c[2];
+    }
     const uint64_t own = rec.mask;
     const bool fl = lane_on(own);
     const Self<RN, OffT> me(rec, lane);
@@ -847,9 +855,7 @@ __global__ __launch_bounds__(512) void k_step(KArgs a) {
     if constexpr (ST == LBM_F16S) {
         if (a.P.f16_stochastic) {
             // keyed on the node's position, not on where the tile is stored
-            const int32_t *c = a.tb.xyz + 4 * (size_t)t;
-            const uint32_t tile_seed =
-                hash32((uint32_t)c[0] + hash32((uint32_t)c[1] + hash32((uint32_t)c[2] + hash32(a.P.launch_counter))));
+            const uint32_t tile_seed = hash32(cx + hash32(cy + hash32(cz + hash32(a.P.launch_counter))));
             const uint32_t seed = hash32(tile_seed + (uint32_t)lane);
             typename C::Pair pair = {};
             store_tile<S, RN, OffT, true, !RN>(a.dst, me, own, fl, lane, [&](int i) {
