@@ -881,6 +881,11 @@ __global__ __launch_bounds__(512) void k_calib(KArgs a) {
     const bool fl = lane_on(own);
     const Self<RN, OffT> me(rec, lane);
     S v[Q];
+    if constexpr (!RN) {
+        // whole-block stores write the solid lanes too: zeros, as the step does
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = S(0);
+    }
     if (fl) {
         if constexpr (KIND == 1) {
 #pragma unroll
