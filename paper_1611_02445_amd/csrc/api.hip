@@ -483,7 +483,11 @@ static int capture_steps(lbm_ctx *c, StepGraph &g, const Phys &P) {
     if (e != hipSuccess) return hip_fail(e, "lbm_step_graphed: begin capture");
     void *x = cur_state(c), *y = c->cur ? c->a : c->b;
     for (int32_t s = 0; s < GRAPH_STEPS && e == hipSuccess; ++s) {
-        e = launch_step(L, P, x, y);
+        // the launch counter's parity sets the direction a step walks the
+        // tiles in (its other use, stochastic rounding, is not graphed)
+        Phys Ps = P;
+        Ps.launch_counter = (uint32_t)s;
+        e = launch_step(L, Ps, x, y);
         std::swap(x, y);
     }
     hipGraph_t graph = nullptr;
