@@ -39,6 +39,7 @@ struct lbm_ctx {
     void *a, *b;        // the two lattices
     int cur;            // 0: a is current, 1: b is current
     void *tables;
+    uint32_t adj_launches = 0;  // adjoint step launches so far
     double *scratch;    // [n_tiles][8] partials + [8] final
     hipStream_t stream;
     Launch L;
@@ -701,7 +702,9 @@ extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *s_tm2, const void *eta_t
     if (c->n_tiles > 0 && (!s_tm2 || !eta_t || !eta_tm1 || !grad_g_tile))
         return fail(LBM_E_INVAL, "lbm_adjoint_step: NULL buffer");
     if (eta_t == eta_tm1 && c->n_tiles > 0) return fail(LBM_E_INVAL, "lbm_adjoint_step: eta buffers must differ");
-    return launched(launch_adjoint_step(c->LA, c->P, s_tm2, eta_t, eta_tm1, grad_g_tile), "lbm_adjoint_step");
+    Phys P = c->P;  // the counter's parity sets the direction the launch walks the tiles in
+    P.launch_counter = c->adj_launches++;
+    return launched(launch_adjoint_step(c->LA, P, s_tm2, eta_t, eta_tm1, grad_g_tile), "lbm_adjoint_step");
 }
 
 extern "C" int lbm_adjoint_final(lbm_ctx *c, const void *eta_1, void *lambda_0) {
