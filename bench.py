@@ -851,7 +851,7 @@ def main():
             "storage": "f64",
             "workgroups": lat.info()["grid_blocks"],
             "tiles_per_workgroup": -(-lat.n_tiles // lat.info()["grid_blocks"]),
-            "tile_order": {0: "morton", 1: "discovery", 2: "slabs4", 3: "slabs8", 4: "morton"}[args.order],
+            "tile_order": {0: "morton", 1: "discovery", 2: "slabs4", 3: "slabs8", 4: "morton", 5: "hilbert"}[args.order],
         },
         "roofline": {
             "bound": "hbm",

@@ -128,7 +128,8 @@ typedef struct lbm_params {
     int32_t tile_order;     /* order in which the device stores and processes the kept tiles:
                                0 = library default (Morton), 1 = discovery order, 2 / 3 = slabs of
                                4 / 8 tile planes with z innermost, 4 = Morton (z-order of the tile
-                               coordinates).  Only the device layout changes; every dense input
+                               coordinates), 5 = Hilbert (a curve whose consecutive tiles are
+                               always face neighbours).  Only the device layout changes; every dense input
                                and output is the same for all orders (FP64 sums may differ in the
                                last bits: their summation order follows the tiles). */
     int32_t wide_offsets;   /* 0 = 32-bit lattice offsets whenever every byte offset of a lattice
@@ -177,7 +178,7 @@ int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *params, lbm_siz
  * returning, so `tiles` may be freed afterwards.  Parameters are validated
  * (LBM_E_INVAL): tau > 1/2, rho0 > 0, known storage and model, f16 scale in
  * [0,30], tiles_per_wg in {0,1,2,4,8}, f16_rounding in {0,1}, tile_order in
- * 0..4, wide_offsets in {0,1}, f32_unshifted in {0,1} (1 only with LBM_F32),
+ * 0..5, wide_offsets in {0,1}, f32_unshifted in {0,1} (1 only with LBM_F32),
  * check_u_max in {0,1};
  * the tables are checked (every neighbour index
  * in [-1, n_tiles), each tile its own centre neighbour, no empty kept tile). */

@@ -90,8 +90,8 @@ int check_params(const lbm_params *p) {
     const int tpw = p->tiles_per_wg;
     if (!(tpw == 0 || tpw == 1 || tpw == 2 || tpw == 4 || tpw == 8))
         return fail(LBM_E_INVAL, "tiles_per_wg must be 0, 1, 2, 4 or 8 (got %d)", tpw);
-    if (p->tile_order < 0 || p->tile_order > 4)
-        return fail(LBM_E_INVAL, "tile_order must be in 0..4 (got %d)", p->tile_order);
+    if (p->tile_order < 0 || p->tile_order > 5)
+        return fail(LBM_E_INVAL, "tile_order must be in 0..5 (got %d)", p->tile_order);
     if (p->wide_offsets != 0 && p->wide_offsets != 1)
         return fail(LBM_E_INVAL, "wide_offsets must be 0 or 1 (got %d)", p->wide_offsets);
     if (p->f32_unshifted != 0 && p->f32_unshifted != 1)
@@ -132,12 +132,44 @@ uint64_t spread3(uint64_t v) {
     return v;
 }
 
+// Position of (x, y, z) along a 3-D Hilbert curve over a 2^b cube, after
+// J. Skilling, "Programming the Hilbert curve" (AIP Conf. Proc. 707, 2004):
+// the coordinates are turned, bit plane by bit plane from the top, into the
+// "transposed" index (undoing the curve's rotations and reflections, then a
+// Gray code), whose bits, taken plane by plane, are the index.
+uint64_t hilbert3(uint32_t x, uint32_t y, uint32_t z, int b) {
+    uint32_t X[3] = {x, y, z};
+    for (uint32_t q = 1u << (b - 1); q > 1; q >>= 1) {
+        const uint32_t low = q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & q) {
+                X[0] ^= low;
+            } else {
+                const uint32_t swap = (X[0] ^ X[i]) & low;
+                X[0] ^= swap;
+                X[i] ^= swap;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t flip = 0;
+    for (uint32_t q = 1u << (b - 1); q > 1; q >>= 1)
+        if (X[2] & q) flip ^= q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= flip;
+    uint64_t h = 0;
+    for (int k = b - 1; k >= 0; --k)
+        h = (h << 3) | ((X[0] >> k & 1u) << 2) | ((X[1] >> k & 1u) << 1) | (X[2] >> k & 1u);
+    return h;
+}
+
 // Order in which the device stores and processes the kept tiles (a
 // permutation of the discovery order).  Consecutive device tiles run at the
 // same time on one XCD, so an order that keeps the six face neighbours close
 // lets the partially shared neighbour lines be found in that XCD's L2.
 //   1 discovery (z outer, y, x inner), 2/3 slabs of 4/8 tile planes with z
-//   innermost inside a slab, 4 Morton (bit-interleaved tile coordinates)
+//   innermost inside a slab, 4 Morton (bit-interleaved tile coordinates),
+//   5 Hilbert (no jumps between consecutive tiles of the curve)
 void processing_order(const lbm_tiles *t, int order, std::vector<int32_t> &perm) {
     const int64_t n = t->n_tiles;
     perm.resize((size_t)n);
@@ -151,6 +183,10 @@ void processing_order(const lbm_tiles *t, int order, std::vector<int32_t> &perm)
         if (order == 2 || order == 3) {
             const uint64_t S = order == 2 ? 4 : 8;
             key[i] = (((z / S) * TY + y) * TX + x) * S + (z % S);
+        } else if (order == 5) {
+            int b = 1;
+            while ((1ull << b) < std::max<uint64_t>(std::max<uint64_t>(TX, TY), (uint64_t)t->tz)) ++b;
+            key[i] = hilbert3((uint32_t)x, (uint32_t)y, (uint32_t)z, b);
         } else {
             key[i] = spread3(x) | spread3(y) << 1 | spread3(z) << 2;
         }

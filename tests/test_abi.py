@@ -45,7 +45,7 @@ def _params(**kw):
 
 @pytest.mark.parametrize("bad", [dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(rho0=0.0),
                                  dict(storage=3), dict(model=4), dict(f16_log2_scale=31), dict(tiles_per_wg=3),
-                                 dict(f16_rounding=2), dict(tile_order=5), dict(wide_offsets=2),
+                                 dict(f16_rounding=2), dict(tile_order=6), dict(wide_offsets=2),
                                  dict(f32_unshifted=2), dict(f32_unshifted=1, storage=0),
                                  dict(check_u_max=2), dict(check_u_max=-1)])
 def test_parameter_validation(bad):

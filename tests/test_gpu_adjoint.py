@@ -326,7 +326,7 @@ def test_adjoint_independent_of_launch_configuration(storage, model):
     g = torch.from_numpy(_force_field(sp, 13)).cuda()
     out = []
     for kw in (dict(), dict(tiles_per_wg=4), dict(tile_order=1), dict(tile_order=2), dict(tile_order=3),
-               dict(tile_order=4, tiles_per_wg=1), dict(tiles_per_wg=8), dict(wide_offsets=True)):
+               dict(tile_order=5), dict(tile_order=4, tiles_per_wg=1), dict(tiles_per_wg=8), dict(wide_offsets=True)):
         lat = new_lattice(s, tau, 7, storage=storage, model=model, **kw)
         lat.set_force(g)
         run = CheckpointedAdjoint(lat, T, 6)

@@ -181,7 +181,7 @@ def test_calibration_kernels():
     assert np.array_equal(g, O.pull(f0, sp, periodic=7))
 
 
-@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
 @pytest.mark.parametrize("storage", ["f64", "f16s"])
 def test_tile_order_bitwise_identical(order, storage):
     """The device tile order changes only where tiles live and when they run."""
