@@ -177,6 +177,10 @@ void processing_order(const lbm_tiles *t, int order, std::vector<int32_t> &perm)
     if (order == 1) return;
     std::vector<uint64_t> key((size_t)n);
     const uint64_t TX = (uint64_t)t->tx, TY = (uint64_t)t->ty;
+    // bits per coordinate of the Hilbert cube (a key of 3 b bits; past 21 it
+    // wraps, which leaves the sort a permutation, only a less local one)
+    int hb = 1;
+    while ((1ull << hb) < std::max<uint64_t>(std::max<uint64_t>(TX, TY), (uint64_t)t->tz)) ++hb;
     for (int64_t i = 0; i < n; ++i) {
         const uint64_t x = (uint64_t)(t->tile_xyz[3 * i] / 4), y = (uint64_t)(t->tile_xyz[3 * i + 1] / 4),
                        z = (uint64_t)(t->tile_xyz[3 * i + 2] / 4);
@@ -184,9 +188,7 @@ void processing_order(const lbm_tiles *t, int order, std::vector<int32_t> &perm)
             const uint64_t S = order == 2 ? 4 : 8;
             key[i] = (((z / S) * TY + y) * TX + x) * S + (z % S);
         } else if (order == 5) {
-            int b = 1;
-            while ((1ull << b) < std::max<uint64_t>(std::max<uint64_t>(TX, TY), (uint64_t)t->tz)) ++b;
-            key[i] = hilbert3((uint32_t)x, (uint32_t)y, (uint32_t)z, b);
+            key[i] = hilbert3((uint32_t)x, (uint32_t)y, (uint32_t)z, hb);
         } else {
             key[i] = spread3(x) | spread3(y) << 1 | spread3(z) << 2;
         }
