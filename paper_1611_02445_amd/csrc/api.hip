@@ -282,7 +282,7 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
     if (!c) return fail(LBM_E_NOMEM, "lbm_create: out of host memory");
     c->params = *params;
     if (c->params.tiles_per_wg == 0) c->params.tiles_per_wg = DEFAULT_TPW;
-    if (c->params.tile_order == 0) c->params.tile_order = 4;  // Morton: best of the four on the sphere packs
+    if (c->params.tile_order == 0) c->params.tile_order = 4;  // Morton: Hilbert ties it, the others trail
     c->nx = tiles->nx;
     c->ny = tiles->ny;
     c->nz = tiles->nz;
