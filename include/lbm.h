@@ -21,7 +21,7 @@
  *   - inside a tile, node (x,y,z) in 0..3 has lane/bit n = x + 4y + 16z
  *     (the XYZ map, Eq. 11);
  *   - tile-order buffers are [n_tiles][components][64], tiles in the
- *     context's device order (see tile_order); lbm_tiles_to_dense converts;
+ *     context's device order (tile_order; lbm_tile_order lists it); lbm_tiles_to_dense converts;
  *   - per-node fields (the force density and its gradient) hold one entry per
  *     fluid node and component: tile t's run of 3k entries (k fluid nodes),
  *     component c of the node with rank r among the tile's fluid nodes (in
@@ -109,6 +109,19 @@ typedef struct lbm_tiles {
 int lbm_build_tiles(const uint8_t *solid, int32_t nx, int32_t ny, int32_t nz, int32_t periodic,
                     lbm_tiles **out);
 void lbm_tiles_free(lbm_tiles *tiles);
+
+/* Device order of the kept tiles.  Within a step every tile reads only the
+ * previous lattice and writes only its own nodes (Section 3.1, Alg. 2), so the
+ * order in which tiles are stored and processed changes no result.  Host
+ * only; no GPU is touched.
+ *   tiles  from lbm_build_tiles; read only
+ *   order  as lbm_params.tile_order, 0..5 (0 = the library default, Morton)
+ *   perm   host int32[n_tiles], caller-owned, written: a context created with
+ *          this order stores and processes tile tiles->tile_xyz[perm[d]] as its
+ *          d-th tile, so row d of a tile-order buffer belongs to that tile
+ * Returns LBM_E_INVAL for a NULL pointer, a malformed tiling or an order
+ * outside 0..5; perm is then untouched. */
+int lbm_tile_order(const lbm_tiles *tiles, int32_t order, int32_t *perm);
 
 /* ------------------------------------------------------------------------
  * Context and device buffers.

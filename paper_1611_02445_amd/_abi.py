@@ -18,7 +18,7 @@ MODEL = {"qc": 0, "quasi-compressible": 0, "inc": 1, "incompressible": 1, "mrt-q
 
 # every symbol include/lbm.h declares
 EXPORTS = [
-    "lbm_build_tiles", "lbm_tiles_free", "lbm_required_bytes", "lbm_create", "lbm_destroy", "lbm_init",
+    "lbm_build_tiles", "lbm_tiles_free", "lbm_tile_order", "lbm_required_bytes", "lbm_create", "lbm_destroy", "lbm_init",
     "lbm_set_force", "lbm_set_boundaries", "lbm_step", "lbm_step_graphed", "lbm_step_buf", "lbm_current_state", "lbm_macroscopic", "lbm_macroscopic_buf",
     "lbm_macroscopic_noalloc",
     "lbm_permeability", "lbm_get_state", "lbm_set_state", "lbm_tiles_to_dense", "lbm_field_to_dense",
@@ -76,6 +76,7 @@ def lib():
     sig = {
         "lbm_build_tiles": ([P, i32, i32, i32, i32, ctypes.POINTER(TP)], ctypes.c_int),
         "lbm_tiles_free": ([TP], None),
+        "lbm_tile_order": ([TP, i32, P], ctypes.c_int),
         "lbm_required_bytes": ([TP, ctypes.POINTER(Params), ctypes.POINTER(Sizes)], ctypes.c_int),
         "lbm_create": ([TP, ctypes.POINTER(Params), P, P, P, P, P, ctypes.POINTER(P)], ctypes.c_int),
         "lbm_destroy": ([P], ctypes.c_int),

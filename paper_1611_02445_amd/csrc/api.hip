@@ -120,6 +120,9 @@ int hip_fail(hipError_t e, const char *what) {
 // tiles (waves) per workgroup when the caller leaves it to the library: 4 was
 // the fastest of 1, 2, 4, 8 for every storage type on the sphere packs
 constexpr int DEFAULT_TPW = 4;
+// device tile order when the caller leaves it to the library: Morton (the
+// Hilbert order ties it, discovery order and the slabs trail)
+constexpr int DEFAULT_TILE_ORDER = 4;
 
 // spread the bits of a 21-bit integer three apart (Morton interleave)
 uint64_t spread3(uint64_t v) {
@@ -226,6 +229,18 @@ hipError_t noalloc_lookup(int device, double **out) {
 
 }  // namespace
 
+extern "C" int lbm_tile_order(const lbm_tiles *tiles, int32_t order, int32_t *perm) {
+    clear_error();
+    int rc;
+    if ((rc = check_tiles(tiles))) return rc;
+    if (order < 0 || order > 5) return fail(LBM_E_INVAL, "lbm_tile_order: order must be in 0..5 (got %d)", order);
+    if (!perm) return fail(LBM_E_INVAL, "lbm_tile_order: NULL output");
+    std::vector<int32_t> p;
+    processing_order(tiles, order == 0 ? DEFAULT_TILE_ORDER : order, p);
+    std::copy(p.begin(), p.end(), perm);
+    return LBM_OK;
+}
+
 extern "C" int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *params, lbm_sizes *out) {
     clear_error();
     int rc;
@@ -282,7 +297,7 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
     if (!c) return fail(LBM_E_NOMEM, "lbm_create: out of host memory");
     c->params = *params;
     if (c->params.tiles_per_wg == 0) c->params.tiles_per_wg = DEFAULT_TPW;
-    if (c->params.tile_order == 0) c->params.tile_order = 4;  // Morton: Hilbert ties it, the others trail
+    if (c->params.tile_order == 0) c->params.tile_order = DEFAULT_TILE_ORDER;
     c->nx = tiles->nx;
     c->ny = tiles->ny;
     c->nz = tiles->nz;

@@ -56,6 +56,13 @@ class Tiling:
     def dense_shape(self):
         return (self.nz, self.ny, self.nx)
 
+    def device_order(self, order=0):
+        """``lbm_tile_order``: the discovery-order tile numbers in the order a
+        context created with ``tile_order=order`` stores and processes them."""
+        perm = np.empty(self.n_tiles, dtype=np.int32)
+        call("lbm_tile_order", self._ptr, int(order), perm.ctypes.data_as(ctypes.c_void_p))
+        return perm
+
     def arrays(self):
         """Copies of the tables as numpy arrays."""
         t = self.t

@@ -181,6 +181,24 @@ def test_calibration_kernels():
     assert np.array_equal(g, O.pull(f0, sp, periodic=7))
 
 
+@pytest.mark.parametrize("order", [1, 2, 3, 4, 5])
+def test_tile_order_buffers_follow_the_listed_order(order):
+    """Row d of a tile-order buffer belongs to the tile that lbm_tile_order
+    lists d-th for the context's order."""
+    import torch
+    s, _ = I.sphere_pack((32, 24, 40), 0.5, 2.0, 5.0, seed=14)
+    lat = new_lattice(s, 0.7, 7, tile_order=order)
+    perm = lat.tiling.device_order(order)
+    n = lat.n_tiles
+    buf = np.repeat(perm.astype(np.float64) + 1.0, 64).reshape(n, 1, 64)
+    dense = lat.tiles_to_dense(torch.from_numpy(buf).cuda(), 1)[0].cpu().numpy()
+    tmap = lat.tiling.arrays()["tile_map"]
+    want = np.repeat(np.repeat(np.repeat(tmap + 1.0, 4, 0), 4, 1), 4, 2)
+    assert s.shape == dense.shape
+    want[s != 0] = 0.0  # solid nodes, in kept tiles too, read 0
+    assert np.array_equal(dense, want)
+
+
 @pytest.mark.parametrize("order", [2, 3, 4, 5])
 @pytest.mark.parametrize("storage", ["f64", "f16s"])
 def test_tile_order_bitwise_identical(order, storage):
