@@ -117,6 +117,17 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(LBM_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// runs f, turning a failed host allocation into LBM_E_NOMEM rather than
+// letting the exception unwind through the C interface
+template <class F>
+int no_throw(const char *what, F &&f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_E_NOMEM, "%s: out of host memory", what);
+    }
+}
+
 // tiles (waves) per workgroup when the caller leaves it to the library: 4 was
 // the fastest of 1, 2, 4, 8 for every storage type on the sphere packs
 constexpr int DEFAULT_TPW = 4;
@@ -235,10 +246,12 @@ extern "C" int lbm_tile_order(const lbm_tiles *tiles, int32_t order, int32_t *pe
     if ((rc = check_tiles(tiles))) return rc;
     if (order < 0 || order > 5) return fail(LBM_E_INVAL, "lbm_tile_order: order must be in 0..5 (got %d)", order);
     if (!perm) return fail(LBM_E_INVAL, "lbm_tile_order: NULL output");
-    std::vector<int32_t> p;
-    processing_order(tiles, order == 0 ? DEFAULT_TILE_ORDER : order, p);
-    std::copy(p.begin(), p.end(), perm);
-    return LBM_OK;
+    return no_throw("lbm_tile_order", [&]() -> int {
+        std::vector<int32_t> p;
+        processing_order(tiles, order == 0 ? DEFAULT_TILE_ORDER : order, p);
+        std::copy(p.begin(), p.end(), perm);
+        return LBM_OK;
+    });
 }
 
 extern "C" int lbm_required_bytes(const lbm_tiles *tiles, const lbm_params *params, lbm_sizes *out) {
@@ -317,7 +330,7 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
     c->noalloc_err = c->device >= 0 ? noalloc_lookup(c->device, &c->noalloc) : hipErrorNoDevice;
 
     const TableLayout lay(n);
-    if (n > 0) {
+    if (n > 0) try {
         // device tile d holds discovery tile perm[d]; neighbour numbers are
         // translated with the inverse permutation
         std::vector<int32_t> perm, inv;
@@ -367,6 +380,9 @@ extern "C" int lbm_create(const lbm_tiles *tiles, const lbm_params *params, void
             delete c;
             return hip_fail(e, "lbm_create: table upload");
         }
+    } catch (const std::bad_alloc &) {
+        delete c;
+        return fail(LBM_E_NOMEM, "lbm_create: out of host memory");
     }
     const unsigned char *tb = reinterpret_cast<const unsigned char *>(tables);
     c->L.stream = c->stream;
@@ -473,40 +489,45 @@ extern "C" int lbm_set_boundaries(lbm_ctx *c, const uint8_t *type_host, double u
         if (type_host[n] > 12) return fail(LBM_E_INVAL, "lbm_set_boundaries: node code %d is not in 0..12", type_host[n]);
         flagged += type_host[n] != 0;
     }
-    // per tile: the mask of its boundary nodes, then their 64 codes
-    std::vector<uint64_t> masks((size_t)c->n_tiles * 9, 0);
-    size_t found = 0;
-    for (int64_t d = 0; d < c->n_tiles; ++d) {
-        const size_t x0 = (size_t)c->corner[3 * d], y0 = (size_t)c->corner[3 * d + 1], z0 = (size_t)c->corner[3 * d + 2];
-        uint8_t *codes = reinterpret_cast<uint8_t *>(&masks[9 * d + 1]);
-        for (int lane = 0; lane < TILE; ++lane) {
-            const size_t x = x0 + (lane & 3), y = y0 + ((lane >> 2) & 3), z = z0 + (lane >> 4);
-            const uint8_t t = type_host[x + nx * (y + ny * z)];
-            if (t) masks[9 * d] |= 1ull << lane;
-            codes[lane] = t;
-            found += t != 0;
+    return no_throw("lbm_set_boundaries", [&]() -> int {
+        // per tile: the mask of its boundary nodes, then their 64 codes
+        std::vector<uint64_t> masks((size_t)c->n_tiles * 9, 0);
+        size_t found = 0;
+        for (int64_t d = 0; d < c->n_tiles; ++d) {
+            const size_t x0 = (size_t)c->corner[3 * d], y0 = (size_t)c->corner[3 * d + 1],
+                         z0 = (size_t)c->corner[3 * d + 2];
+            uint8_t *codes = reinterpret_cast<uint8_t *>(&masks[9 * d + 1]);
+            for (int lane = 0; lane < TILE; ++lane) {
+                const size_t x = x0 + (lane & 3), y = y0 + ((lane >> 2) & 3), z = z0 + (lane >> 4);
+                const uint8_t t = type_host[x + nx * (y + ny * z)];
+                if (t) masks[9 * d] |= 1ull << lane;
+                codes[lane] = t;
+                found += t != 0;
+            }
         }
-    }
-    if (found != flagged) return fail(LBM_E_INVAL, "lbm_set_boundaries: %zu flagged nodes lie in dropped tiles", flagged - found);
-    // ... and fluid inside its tile
-    std::vector<TileRec> rec((size_t)c->n_tiles);
-    hipError_t e = hipMemcpyAsync(rec.data(), c->L.tb.rec, rec.size() * sizeof(TileRec), hipMemcpyDeviceToHost,
-                                  c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_fail(e, "lbm_set_boundaries: reading tile masks");
-    for (int64_t d = 0; d < c->n_tiles; ++d)
-        if (masks[9 * d] & ~rec[d].mask) return fail(LBM_E_INVAL, "lbm_set_boundaries: a flagged node is solid");
-    if (c->n_tiles > 0) {
-        e = hipMemcpyAsync(bc_tile_buf, masks.data(), masks.size() * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream);
+        if (found != flagged)
+            return fail(LBM_E_INVAL, "lbm_set_boundaries: %zu flagged nodes lie in dropped tiles", flagged - found);
+        // ... and fluid inside its tile
+        std::vector<TileRec> rec((size_t)c->n_tiles);
+        hipError_t e = hipMemcpyAsync(rec.data(), c->L.tb.rec, rec.size() * sizeof(TileRec), hipMemcpyDeviceToHost,
+                                      c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        if (e != hipSuccess) return hip_fail(e, "lbm_set_boundaries: upload");
-    }
-    c->P.bc = reinterpret_cast<const uint64_t *>(bc_tile_buf);
-    c->P.bc_u[0] = ux;
-    c->P.bc_u[1] = uy;
-    c->P.bc_u[2] = uz;
-    c->P.bc_rho = rho_out;
-    return LBM_OK;
+        if (e != hipSuccess) return hip_fail(e, "lbm_set_boundaries: reading tile masks");
+        for (int64_t d = 0; d < c->n_tiles; ++d)
+            if (masks[9 * d] & ~rec[d].mask) return fail(LBM_E_INVAL, "lbm_set_boundaries: a flagged node is solid");
+        if (c->n_tiles > 0) {
+            e = hipMemcpyAsync(bc_tile_buf, masks.data(), masks.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
+                               c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) return hip_fail(e, "lbm_set_boundaries: upload");
+        }
+        c->P.bc = reinterpret_cast<const uint64_t *>(bc_tile_buf);
+        c->P.bc_u[0] = ux;
+        c->P.bc_u[1] = uy;
+        c->P.bc_u[2] = uz;
+        c->P.bc_rho = rho_out;
+        return LBM_OK;
+    });
 }
 
 extern "C" int lbm_step(lbm_ctx *c, int32_t n) {

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "common.hpp"
@@ -90,40 +91,47 @@ extern "C" int lbm_build_tiles(const uint8_t *solid, int32_t nx, int32_t ny, int
     std::vector<int32_t> corners;
     int64_t n_fluid = 0;
     const size_t sx = 1, sy = (size_t)nx, sz = (size_t)nx * (size_t)ny;
-    for (int64_t bz = 0; bz < tz; ++bz)
-        for (int64_t by = 0; by < ty; ++by)
-            for (int64_t bx = 0; bx < tx; ++bx) {
-                uint64_t m = 0;
-                for (int z = 0; z < 4; ++z) {
-                    const int64_t Z = 4 * bz + z;
-                    if (Z >= nz) continue;  // padding: solid
-                    for (int y = 0; y < 4; ++y) {
-                        const int64_t Y = 4 * by + y;
-                        if (Y >= ny) continue;
-                        const uint8_t *row = solid + (size_t)Z * sz + (size_t)Y * sy;
-                        for (int x = 0; x < 4; ++x) {
-                            const int64_t X = 4 * bx + x;
-                            if (X >= nx) continue;
-                            if (!row[(size_t)X * sx]) m |= 1ull << (x + 4 * y + 16 * z);
+    // pass 1 grows the two lists: an allocation failure there is reported,
+    // not thrown through the C interface
+    try {
+        for (int64_t bz = 0; bz < tz; ++bz)
+            for (int64_t by = 0; by < ty; ++by)
+                for (int64_t bx = 0; bx < tx; ++bx) {
+                    uint64_t m = 0;
+                    for (int z = 0; z < 4; ++z) {
+                        const int64_t Z = 4 * bz + z;
+                        if (Z >= nz) continue;  // padding: solid
+                        for (int y = 0; y < 4; ++y) {
+                            const int64_t Y = 4 * by + y;
+                            if (Y >= ny) continue;
+                            const uint8_t *row = solid + (size_t)Z * sz + (size_t)Y * sy;
+                            for (int x = 0; x < 4; ++x) {
+                                const int64_t X = 4 * bx + x;
+                                if (X >= nx) continue;
+                                if (!row[(size_t)X * sx]) m |= 1ull << (x + 4 * y + 16 * z);
+                            }
                         }
                     }
-                }
-                const int64_t g = bx + tx * (by + ty * bz);
-                if (m) {
-                    if ((int64_t)masks.size() >= INT32_MAX) {
-                        lbm_tiles_free(t);
-                        return fail(LBM_E_RANGE, "lbm_build_tiles: more than INT32_MAX non-empty tiles");
+                    const int64_t g = bx + tx * (by + ty * bz);
+                    if (m) {
+                        if ((int64_t)masks.size() >= INT32_MAX) {
+                            lbm_tiles_free(t);
+                            return fail(LBM_E_RANGE, "lbm_build_tiles: more than INT32_MAX non-empty tiles");
+                        }
+                        t->tile_map[g] = (int32_t)masks.size();
+                        masks.push_back(m);
+                        corners.push_back((int32_t)(4 * bx));
+                        corners.push_back((int32_t)(4 * by));
+                        corners.push_back((int32_t)(4 * bz));
+                        n_fluid += __builtin_popcountll(m);
+                    } else {
+                        t->tile_map[g] = -1;
                     }
-                    t->tile_map[g] = (int32_t)masks.size();
-                    masks.push_back(m);
-                    corners.push_back((int32_t)(4 * bx));
-                    corners.push_back((int32_t)(4 * by));
-                    corners.push_back((int32_t)(4 * bz));
-                    n_fluid += __builtin_popcountll(m);
-                } else {
-                    t->tile_map[g] = -1;
                 }
-            }
+    } catch (const std::bad_alloc &) {
+        lbm_tiles_free(t);
+        return fail(LBM_E_NOMEM, "lbm_build_tiles: out of host memory");
+    }
     const int64_t n = (int64_t)masks.size();
     t->n_tiles = (int32_t)n;
     t->n_fluid = n_fluid;
