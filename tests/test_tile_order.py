@@ -106,3 +106,17 @@ def test_orders_outside_the_range_are_rejected(order):
     t = _dense(2, 2, 2)
     with pytest.raises(LbmError, match="LBM_E_INVAL.*order"):
         t.device_order(order)
+
+
+def test_null_arguments_are_rejected_and_leave_the_output_untouched():
+    import ctypes
+    from paper_1611_02445_amd._abi import call
+    t = _dense(2, 2, 2)
+    perm = np.full(t.n_tiles, -7, dtype=np.int32)
+    with pytest.raises(LbmError, match="LBM_E_INVAL"):
+        call("lbm_tile_order", None, 0, perm.ctypes.data_as(ctypes.c_void_p))
+    with pytest.raises(LbmError, match="LBM_E_INVAL.*NULL"):
+        call("lbm_tile_order", t._ptr, 0, None)
+    with pytest.raises(LbmError, match="LBM_E_INVAL"):
+        call("lbm_tile_order", t._ptr, 9, perm.ctypes.data_as(ctypes.c_void_p))
+    assert np.all(perm == -7)
