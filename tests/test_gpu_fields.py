@@ -1,7 +1,8 @@
 """Per-node fields (the force density and the force gradient) stored one
 entry per fluid node and component: the round trip through lbm_set_force and
-lbm_field_to_dense is exact, pad entries are zero, and a per-node force
-gives the oracle's step on partly solid tiles for every storage type."""
+lbm_field_to_dense is exact (default, discovery and Hilbert tile orders), pad
+entries are zero, and a per-node force gives the oracle's step on partly
+solid tiles for every storage type."""
 import numpy as np
 import pytest
 
@@ -13,14 +14,15 @@ from helpers import log, new_lattice, padded, perturbed_state
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("order", [0, 1, 5])
 @pytest.mark.parametrize("storage,dtype", [("f64", 0), ("f32", 1), ("f16s", 1)])
-def test_force_field_round_trip(storage, dtype):
+def test_force_field_round_trip(storage, dtype, order):
     import torch
     s, _ = I.sphere_pack((20, 24, 16), 0.45, 2.0, 5.0, seed=71)
     sp = padded(s, 7)
     rng = np.random.default_rng(72)
     g = rng.normal(0.0, 1e-5, (3,) + sp.shape)
-    lat = new_lattice(s, 0.8, 7, storage=storage, rho0=1.25)
+    lat = new_lattice(s, 0.8, 7, storage=storage, rho0=1.25, tile_order=order)
     lat.set_force(torch.from_numpy(g).cuda())
     back = lat.field_to_dense(lat.force_buf, dtype).cpu().numpy()
     ref = 1.25 * g
